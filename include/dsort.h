@@ -1,0 +1,127 @@
+/*
+ * dsort: deterministic sample sort ("GPU Bucket Sort", Algorithm 1 of Dehne & Zaboli,
+ * "Deterministic Sample Sort For GPUs", Section 4) for AMD Instinct MI355X (gfx950).
+ *
+ * Plain C ABI: every entry point is extern "C", takes plain pointers and sizes, and never
+ * throws.  Device pointers are HIP device allocations owned by the caller; `stream` is a
+ * hipStream_t passed as void* (NULL = the default stream).  Sorting calls only enqueue work on
+ * `stream` and return; kernel faults surface at the caller's next synchronisation.
+ *
+ * Problem statement (Algorithm 1, "Input"/"Output"): an array A of n items in device memory is
+ * sorted in place.  Key order: uint32 and uint64 keys by unsigned value; float32 keys by IEEE
+ * 754 totalOrder of their bit patterns (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN; the
+ * output holds the input bit patterns, permuted).  Key/value sorts are stable: equal keys keep
+ * their input order.  Algorithm 1 compares items under the total order (key, sublist, rank), so
+ * the bucket-size bound of Section 4 holds for any input, repeated keys included.
+ *
+ * Status codes are the DSORT_* values below; dsort_strerror() describes them.
+ */
+#ifndef DSORT_H
+#define DSORT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Key types. */
+enum {
+    DSORT_U32 = 1, /* uint32_t keys */
+    DSORT_U64 = 2, /* uint64_t keys */
+    DSORT_F32 = 3  /* float keys, ordered by IEEE totalOrder */
+};
+
+/* Status codes (0 = success, negative = failure). */
+enum {
+    DSORT_OK = 0,
+    DSORT_E_INVALID = -1,     /* bad argument: NULL pointer, unknown type, n > plan maximum, ... */
+    DSORT_E_UNSUPPORTED = -2, /* valid request this build cannot serve (e.g. tuning infeasible) */
+    DSORT_E_NOMEM = -3,       /* host allocation failed */
+    DSORT_E_HIP = -4,         /* a HIP runtime call or kernel launch failed */
+    DSORT_E_CAPACITY = -5,    /* request larger than a configured capacity */
+    DSORT_E_TICKET = -6       /* unknown ticket */
+};
+
+/* Optional tuning.  Zero in a field means "choose automatically".
+ *  sublist_len  L  of the first level (Step 1: the sublist length n/m), power of two;
+ *  samples      s  of the first level (Step 3: samples per sublist = number of buckets),
+ *                  power of two dividing L;
+ *  sublist_len2, samples2: the same for the second level (Step 9 run as a segmented sort);
+ *  levels       0 = auto, 1 = force one level (Step 9 sorts each bucket in one workgroup),
+ *               2 = force two levels. */
+typedef struct {
+    uint32_t sublist_len;
+    uint32_t samples;
+    uint32_t sublist_len2;
+    uint32_t samples2;
+    uint32_t levels;
+} dsort_tuning_t;
+
+typedef struct dsort_plan_s *dsort_plan_t;
+
+/* Plan a sort of up to `max_items` items of key type `key_type` (DSORT_U32/U64/F32), with
+ * (`with_values` = 1) or without (0) a uint32 value per key.  `max_segments` bounds the
+ * segment count of dsort_segmented (0 if unused).  `tuning` may be NULL.
+ * On success *out receives the plan (host memory, owned by the caller until
+ * dsort_plan_destroy) and *workspace_bytes the size of the device workspace every call
+ * with this plan needs.  The plan holds host state only and allocates no device memory.
+ * Errors: DSORT_E_INVALID (NULL out/workspace_bytes, bad type, max_items above the limit
+ * 2^32 - 2^16), DSORT_E_UNSUPPORTED (tuning cannot be realised), DSORT_E_NOMEM. */
+int dsort_plan(dsort_plan_t *out, int key_type, int with_values, uint64_t max_items,
+               uint64_t max_segments, const dsort_tuning_t *tuning, size_t *workspace_bytes);
+
+/* Sort `n` keys at `d_keys` in place (Algorithm 1, Steps 1-9).  `d_workspace` must hold the
+ * plan's workspace_bytes of device memory, 256-byte aligned; its contents on entry do not
+ * matter and on return hold the intermediates of the last call (see dsort_plan_geometry).
+ * n = 0 and n = 1 are no-ops.  Requires a plan made with with_values = 0.
+ * Errors: DSORT_E_INVALID (NULL plan/pointers, n > max_items, plan with values),
+ * DSORT_E_HIP (a launch failed).  One plan + workspace pair serves one stream at a time. */
+int dsort_keys(dsort_plan_t plan, void *d_keys, uint64_t n, void *d_workspace, void *stream);
+
+/* Stable sort of `n` (key, value) pairs in place: d_keys as for dsort_keys, d_values holds n
+ * uint32 values that move with their keys; equal keys keep input order.  Requires a plan made
+ * with with_values = 1.  Errors as for dsort_keys. */
+int dsort_pairs(dsort_plan_t plan, void *d_keys, uint32_t *d_values, uint64_t n,
+                void *d_workspace, void *stream);
+
+/* Release a plan (NULL is accepted). */
+int dsort_plan_destroy(dsort_plan_t plan);
+
+/* Static description of the string for a status code (never NULL). */
+const char *dsort_strerror(int status);
+
+/* Geometry the plan uses for a call with `n` items, and where the intermediates of the first
+ * level live inside the workspace after such a call (byte offsets from d_workspace).
+ * levels: 0 = the whole input fits one workgroup tile and is sorted directly;
+ *         1 = Algorithm 1 once, Step 9 sorts every bucket inside one workgroup;
+ *         2 = Step 9 of the first level is itself Algorithm 1, run on every bucket.
+ * Sample arrays hold composites (key, i*L + r) (32-bit keys: one uint64 (key << 32) | pos;
+ * 64-bit keys: 16 bytes {uint64 key, uint32 pos, uint32 unused}).  Count and offset matrices
+ * are m x s row-major uint32; row i belongs to sublist i; offsets are absolute positions. */
+typedef struct {
+    uint64_t n;
+    uint32_t levels;
+    uint32_t sublist_len, samples, sublists;       /* L, s, m of level 1 */
+    uint32_t sublist_len2, samples2, max_tiles2;   /* L, s and a bound on sublists of level 2 */
+    uint32_t bucket_capacity;                      /* largest bucket one workgroup sorts */
+    uint32_t bucket_bound;                         /* 2 n'/s - m of level 1 */
+    uint32_t sample_bytes;                         /* bytes per sample composite */
+    uint32_t sample_sort_global;                   /* 1: Step 4 uses the multi-kernel merge */
+    uint64_t off_status;          /* uint32 error flags raised by kernels (0 = none) */
+    uint64_t off_samples;         /* level-1 samples in sublist order (Step 3) */
+    uint64_t off_sorted_samples;  /* level-1 samples after Step 4 */
+    uint64_t off_counts;          /* a_ij (Step 6) */
+    uint64_t off_offsets;         /* l_ij (Step 7) */
+    uint64_t off_buckets;         /* level-1 buckets as {uint32 begin, uint32 size} (Step 8) */
+    uint64_t workspace_bytes;     /* bytes this n needs (<= the plan's workspace size) */
+} dsort_geometry_t;
+
+int dsort_plan_geometry(dsort_plan_t plan, uint64_t n, dsort_geometry_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSORT_H */

@@ -1,0 +1,237 @@
+"""dsort: deterministic sample sort for AMD Instinct MI355X (gfx950).
+
+Thin ctypes binding over ``libdsort.so`` (C ABI in include/dsort.h).  Every step of the sort runs
+in the library's HIP kernels; this module only marshals arguments.  PyTorch supplies device
+memory (keys, values, workspace) and the stream.  There is no fallback: if the library is not
+built, or is asked to sort host tensors, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+__all__ = [
+    "U32", "U64", "F32", "DsortError", "Tuning", "Plan", "load_library", "sort", "sort_pairs",
+    "strerror", "EXPORTED_SYMBOLS",
+]
+
+U32, U64, F32 = 1, 2, 3
+OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP, E_CAPACITY, E_TICKET = 0, -1, -2, -3, -4, -5, -6
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdsort.so")
+
+EXPORTED_SYMBOLS = (
+    "dsort_plan", "dsort_keys", "dsort_pairs", "dsort_plan_destroy", "dsort_strerror",
+    "dsort_plan_geometry",
+)
+
+
+class DsortError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} ({status})" if what else strerror(status))
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("sublist_len", ctypes.c_uint32), ("samples", ctypes.c_uint32),
+                ("sublist_len2", ctypes.c_uint32), ("samples2", ctypes.c_uint32),
+                ("levels", ctypes.c_uint32)]
+
+
+class _Geometry(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("levels", ctypes.c_uint32),
+                ("sublist_len", ctypes.c_uint32), ("samples", ctypes.c_uint32),
+                ("sublists", ctypes.c_uint32), ("sublist_len2", ctypes.c_uint32),
+                ("samples2", ctypes.c_uint32), ("max_tiles2", ctypes.c_uint32),
+                ("bucket_capacity", ctypes.c_uint32), ("bucket_bound", ctypes.c_uint32),
+                ("sample_bytes", ctypes.c_uint32), ("sample_sort_global", ctypes.c_uint32),
+                ("off_status", ctypes.c_uint64), ("off_samples", ctypes.c_uint64),
+                ("off_sorted_samples", ctypes.c_uint64), ("off_counts", ctypes.c_uint64),
+                ("off_offsets", ctypes.c_uint64), ("off_buckets", ctypes.c_uint64),
+                ("workspace_bytes", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libdsort.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libdsort.so is not built ({path}); run `python -m "
+                           f"paper_1002_4464_amd.build` or __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P, U64_, I = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+    lib.dsort_plan.argtypes = [ctypes.POINTER(P), I, I, U64_, U64_, ctypes.POINTER(Tuning),
+                               ctypes.POINTER(ctypes.c_size_t)]
+    lib.dsort_plan.restype = I
+    lib.dsort_keys.argtypes = [P, P, U64_, P, P]
+    lib.dsort_keys.restype = I
+    lib.dsort_pairs.argtypes = [P, P, P, U64_, P, P]
+    lib.dsort_pairs.restype = I
+    lib.dsort_plan_destroy.argtypes = [P]
+    lib.dsort_plan_destroy.restype = I
+    lib.dsort_strerror.argtypes = [I]
+    lib.dsort_strerror.restype = ctypes.c_char_p
+    lib.dsort_plan_geometry.argtypes = [P, U64_, ctypes.POINTER(_Geometry)]
+    lib.dsort_plan_geometry.restype = I
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    return load_library().dsort_strerror(status).decode()
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise DsortError(rc, what)
+
+
+@dataclass
+class Geometry:
+    n: int
+    levels: int
+    sublist_len: int
+    samples: int
+    sublists: int
+    sublist_len2: int
+    samples2: int
+    max_tiles2: int
+    bucket_capacity: int
+    bucket_bound: int
+    sample_bytes: int
+    sample_sort_global: bool
+    off_status: int
+    off_samples: int
+    off_sorted_samples: int
+    off_counts: int
+    off_offsets: int
+    off_buckets: int
+    workspace_bytes: int
+
+
+class Plan:
+    """A sort plan (host state) plus, on demand, a torch-allocated device workspace."""
+
+    def __init__(self, key_type: int, values: bool, max_items: int, tuning: Tuning | None = None,
+                 max_segments: int = 0):
+        lib = load_library()
+        self._lib = lib
+        self.key_type = key_type
+        self.values = bool(values)
+        self.max_items = int(max_items)
+        h = ctypes.c_void_p()
+        ws = ctypes.c_size_t()
+        rc = lib.dsort_plan(ctypes.byref(h), key_type, int(self.values), self.max_items,
+                            max_segments, ctypes.byref(tuning) if tuning is not None else None,
+                            ctypes.byref(ws))
+        _check(rc, "dsort_plan")
+        self._h = h
+        self.workspace_bytes = int(ws.value)
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.dsort_plan_destroy(h)
+            self._h = None
+
+    def geometry(self, n: int) -> Geometry:
+        g = _Geometry()
+        _check(self._lib.dsort_plan_geometry(self._h, int(n), ctypes.byref(g)),
+               "dsort_plan_geometry")
+        return Geometry(*[getattr(g, f) for f, _ in _Geometry._fields_])
+
+    def workspace(self, device):
+        """A workspace tensor (uint8, plan.workspace_bytes) on ``device``, cached."""
+        import torch
+        if self._ws is None or self._ws.device != torch.device(device):
+            self._ws = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8,
+                                   device=device)
+        return self._ws
+
+    @staticmethod
+    def _dev_ptr(t, itemsize: int, what: str) -> int:
+        if not t.is_cuda:
+            raise ValueError(f"{what} must be a device tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        if t.element_size() != itemsize:
+            raise ValueError(f"{what} must have {itemsize}-byte elements")
+        return t.data_ptr()
+
+    def _stream(self, stream, device):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        return ctypes.c_void_p(stream.cuda_stream)
+
+    def sort_keys(self, keys, workspace=None, stream=None):
+        """Sorts ``keys`` (a contiguous device tensor) in place; returns it."""
+        if self.values:
+            raise ValueError("plan was made for key/value sorts")
+        ksz = 8 if self.key_type == U64 else 4
+        kp = self._dev_ptr(keys, ksz, "keys")
+        ws = workspace if workspace is not None else self.workspace(keys.device)
+        rc = self._lib.dsort_keys(self._h, ctypes.c_void_p(kp), keys.numel(),
+                                  ctypes.c_void_p(ws.data_ptr()), self._stream(stream, keys.device))
+        _check(rc, "dsort_keys")
+        return keys
+
+    def sort_pairs(self, keys, values, workspace=None, stream=None):
+        """Stable sort of (keys, values) in place (values: 4-byte elements); returns both."""
+        if not self.values:
+            raise ValueError("plan was made for keys-only sorts")
+        if values.numel() != keys.numel():
+            raise ValueError("keys and values differ in length")
+        ksz = 8 if self.key_type == U64 else 4
+        kp = self._dev_ptr(keys, ksz, "keys")
+        vp = self._dev_ptr(values, 4, "values")
+        ws = workspace if workspace is not None else self.workspace(keys.device)
+        rc = self._lib.dsort_pairs(self._h, ctypes.c_void_p(kp), ctypes.c_void_p(vp),
+                                   keys.numel(), ctypes.c_void_p(ws.data_ptr()),
+                                   self._stream(stream, keys.device))
+        _check(rc, "dsort_pairs")
+        return keys, values
+
+
+def _key_type_of(t, key_type):
+    if key_type is not None:
+        return key_type
+    import torch
+    if t.dtype == torch.float32:
+        return F32
+    if t.element_size() == 8:
+        return U64
+    if t.element_size() == 4:
+        return U32
+    raise ValueError(f"unsupported key dtype {t.dtype}")
+
+
+_plans: dict = {}
+
+
+def _plan_for(key_type: int, values: bool, n: int) -> Plan:
+    cap = 1 << max(10, (max(n, 2) - 1).bit_length())
+    k = (key_type, values, cap)
+    if k not in _plans:
+        _plans[k] = Plan(key_type, values, cap)
+    return _plans[k]
+
+
+def sort(keys, key_type: int | None = None, stream=None):
+    """Sorts a contiguous device tensor in place (4-byte elements: uint32 order, or float32
+    totalOrder for float32 tensors; 8-byte elements: uint64 order) and returns it."""
+    kt = _key_type_of(keys, key_type)
+    return _plan_for(kt, False, keys.numel()).sort_keys(keys, stream=stream)
+
+
+def sort_pairs(keys, values, key_type: int | None = None, stream=None):
+    """Stable key/value sort in place; values are 4-byte elements."""
+    kt = _key_type_of(keys, key_type)
+    return _plan_for(kt, True, keys.numel()).sort_pairs(keys, values, stream=stream)

@@ -1,0 +1,64 @@
+// Internal declarations shared by the host planner (plan.cpp) and the HIP pipeline
+// (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/dsort.h"
+
+namespace dsort {
+
+// Per (key type, values) capacities of the workgroup sorts.  They must match the kernel
+// instantiations in kernels.hip.
+struct Caps {
+    uint32_t tile_max;   // largest sublist length L one workgroup sorts in Step 2
+    uint32_t tile_e;     // items per thread of that sort
+    uint32_t final_cap;  // largest bucket one workgroup sorts in Step 9
+    uint32_t final_e;
+    uint32_t samp_cap;   // largest sample set one workgroup sorts in Step 4
+    uint32_t samp_e;
+    uint32_t key_bytes;
+    uint32_t samp_bytes; // bytes of one sample composite
+};
+
+Caps caps_for(int key_type, bool values);
+
+// Everything one call needs: the level structure, the launch geometry and the workspace map.
+struct Geom {
+    int key_type = 0;
+    bool values = false;
+    uint64_t n = 0;
+    int levels = -1;  // -1: nothing to do (n <= 1); 0: one tile; 1; 2
+    Caps caps{};
+
+    // level 1
+    uint32_t L1 = 0, s1 = 0, m1 = 0;
+    uint32_t beta1 = 0;
+    bool samp_global = false;  // Step 4 as chunk sorts + merge rounds
+    uint32_t samp_rounds = 0;
+    bool scan_large = false;   // Step 7 as three kernels over row blocks
+    uint32_t scan_rb = 0, scan_nrb = 0;
+    // level 2
+    uint32_t L2 = 0, s2 = 0, m2max = 0, tiles2max = 0;
+    uint32_t final_buckets = 0;
+
+    // workspace byte offsets
+    size_t o_status = 0, o_wkeys = 0, o_wvals = 0;
+    size_t o_samp = 0, o_samp_sorted = 0, o_samp_tmp = 0;
+    size_t o_counts = 0, o_offs = 0, o_partial = 0;
+    size_t o_buckets1 = 0, o_tileoff2 = 0;
+    size_t o_samp2 = 0, o_samp2_sorted = 0, o_counts2 = 0, o_offs2 = 0;
+    size_t o_final = 0;
+    size_t total = 0;
+};
+
+// Computes the geometry for n items.  Returns DSORT_OK or DSORT_E_UNSUPPORTED.
+int make_geom(int key_type, bool values, uint64_t n, const dsort_tuning_t &tuning, Geom &g);
+
+// Enqueues the whole pipeline (kernels.hip).  Pointers are device pointers.
+int run_pipeline(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, void *stream);
+
+constexpr uint64_t kMaxItems = (1ull << 32) - (1ull << 16);
+
+}  // namespace dsort

@@ -1,0 +1,366 @@
+// Host side of the C ABI: argument checking, the choice of (L, s) per level, and the
+// workspace map.  No HIP runtime call happens here, so all of it runs without a GPU.
+//
+// Sizes follow Section 4 of the paper: m = ceil(n/L) sublists of L items, s samples per
+// sublist, and after Step 8 buckets B_j with m <= |B_j| <= 2n'/s - m (n' = mL, the padded
+// size), which is the exact form of the paper's "at most 2n/s" bound under the total order
+// (key, sublist, rank).  Every bucket that Step 9 hands to one workgroup must therefore obey
+// 2n'/s - m <= capacity, which fixes the smallest admissible s.  When that s would make the
+// sample set too large (more than 1/32 of the data), Step 9 instead runs Algorithm 1 again on
+// each bucket (a second level), whose buckets then fit one workgroup.
+#include <new>
+#include <stdlib.h>
+#include <string.h>
+
+#include "dsort_internal.h"
+
+namespace dsort {
+
+namespace {
+
+bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Largest bucket Step 8 can produce with m sublists of L items and s samples per sublist.
+uint64_t bucket_bound(uint64_t m, uint64_t L, uint64_t s) { return 2 * m * L / s - m; }
+
+constexpr uint32_t kScanSmallRows = 1024;  // one workgroup scans up to this many sublists
+constexpr uint32_t kScanRowBlock = 64;
+constexpr uint64_t kMaxSamples = 1024;  // per-sublist tables live in LDS
+
+}  // namespace
+
+Caps caps_for(int key_type, bool values) {
+    Caps c{};
+    if (key_type == DSORT_U64) {
+        c.key_bytes = 8;
+        c.samp_bytes = 16;
+        c.samp_cap = 8192;
+        c.samp_e = 8;
+        if (values) {
+            c.tile_max = 8192; c.tile_e = 8;
+            c.final_cap = 8192; c.final_e = 8;
+        } else {
+            c.tile_max = 16384; c.tile_e = 16;
+            c.final_cap = 16384; c.final_e = 16;
+        }
+    } else {
+        c.key_bytes = 4;
+        c.samp_bytes = 8;
+        c.samp_cap = 16384;
+        c.samp_e = 16;
+        if (values) {
+            c.tile_max = 16384; c.tile_e = 16;
+            c.final_cap = 16384; c.final_e = 16;
+        } else {
+            c.tile_max = 16384; c.tile_e = 16;
+            c.final_cap = 32768; c.final_e = 32;
+        }
+    }
+    return c;
+}
+
+int make_geom(int key_type, bool values, uint64_t n, const dsort_tuning_t &tu, Geom &g) {
+    g = Geom{};
+    g.key_type = key_type;
+    g.values = values;
+    g.n = n;
+    g.caps = caps_for(key_type, values);
+    const Caps &c = g.caps;
+    g.o_status = 0;
+    size_t off = 256;
+    if (n <= 1) {
+        g.levels = -1;
+        g.total = off;
+        return DSORT_OK;
+    }
+    const bool tuned = tu.sublist_len || tu.samples || tu.sublist_len2 || tu.samples2 || tu.levels;
+    if (tu.levels > 2) return DSORT_E_UNSUPPORTED;
+    if (!tuned && n <= c.final_cap) {
+        g.levels = 0;
+        g.total = off;
+        return DSORT_OK;
+    }
+
+    const uint64_t L1 = tu.sublist_len ? tu.sublist_len : c.tile_max;
+    if (!is_pow2(L1) || L1 < c.tile_e || L1 > c.tile_max) return DSORT_E_UNSUPPORTED;
+    if (tu.samples && (!is_pow2(tu.samples) || tu.samples > L1 || tu.samples > kMaxSamples))
+        return DSORT_E_UNSUPPORTED;
+    const uint64_t m1 = ceil_div(n, L1);
+    if (m1 * L1 > kMaxItems + L1) return DSORT_E_UNSUPPORTED;
+
+    // --- one level: the smallest s whose bucket bound fits one workgroup.
+    uint64_t s1 = 0;
+    bool one = false;
+    if (tu.levels != 2) {
+        if (tu.samples) {
+            s1 = tu.samples;
+            one = bucket_bound(m1, L1, s1) <= c.final_cap;
+            if (!one && tu.levels == 1) return DSORT_E_UNSUPPORTED;
+        } else {
+            uint64_t smax = tu.levels == 1 ? L1 : L1 / 32;
+            if (smax > kMaxSamples) smax = kMaxSamples;
+            for (uint64_t s = 1; s <= smax; s <<= 1)
+                if (bucket_bound(m1, L1, s) <= c.final_cap) { s1 = s; one = true; break; }
+            if (!one && tu.levels == 1) return DSORT_E_UNSUPPORTED;
+        }
+    }
+
+    uint64_t L2 = 0, s2 = 0, m2max = 0;
+    if (!one) {
+        // --- two levels: the smallest s1 for which every bucket can be sorted by one more
+        // level whose samples fit one workgroup (Step 4 of the second level stays local).
+        L2 = tu.sublist_len2 ? tu.sublist_len2 : c.tile_max;
+        if (!is_pow2(L2) || L2 < c.tile_e || L2 > c.tile_max) return DSORT_E_UNSUPPORTED;
+        if (tu.samples2 && (!is_pow2(tu.samples2) || tu.samples2 > L2 || tu.samples2 > kMaxSamples))
+            return DSORT_E_UNSUPPORTED;
+        bool found = false;
+        const uint64_t lo = tu.samples ? tu.samples : 2;
+        const uint64_t hi = tu.samples ? tu.samples : (L1 / 8 < kMaxSamples ? L1 / 8 : kMaxSamples);
+        for (uint64_t s = lo; s <= hi && !found; s <<= 1) {
+            const uint64_t b1 = bucket_bound(m1, L1, s);
+            const uint64_t mm = ceil_div(b1, L2);
+            const uint64_t t_lo = tu.samples2 ? tu.samples2 : 1;
+            const uint64_t t_hi = tu.samples2 ? tu.samples2 : (L2 < kMaxSamples ? L2 : kMaxSamples);
+            for (uint64_t t = t_lo; t <= t_hi; t <<= 1) {
+                if (mm * (2 * L2 / t - 1) <= c.final_cap) {
+                    if (mm * t <= c.samp_cap) {
+                        s1 = s; s2 = t; m2max = mm; found = true;
+                    }
+                    break;
+                }
+            }
+        }
+        if (!found) return DSORT_E_UNSUPPORTED;
+    }
+
+    g.L1 = (uint32_t)L1;
+    g.s1 = (uint32_t)s1;
+    g.m1 = (uint32_t)m1;
+    g.beta1 = (uint32_t)bucket_bound(m1, L1, s1);
+    const uint64_t sm = m1 * s1;
+    g.samp_global = sm > c.samp_cap;
+    if (g.samp_global) {
+        uint32_t r = 0;
+        for (uint64_t run = c.samp_cap; run < sm; run <<= 1) ++r;
+        g.samp_rounds = r;
+    }
+    g.scan_large = m1 > kScanSmallRows;
+    g.scan_rb = kScanRowBlock;
+    g.scan_nrb = (uint32_t)ceil_div(m1, kScanRowBlock);
+
+    if (one) {
+        g.levels = 1;
+        g.final_buckets = (uint32_t)s1;
+    } else {
+        g.levels = 2;
+        g.L2 = (uint32_t)L2;
+        g.s2 = (uint32_t)s2;
+        g.m2max = (uint32_t)m2max;
+        g.tiles2max = (uint32_t)(ceil_div(n, L2) + s1);
+        g.final_buckets = (uint32_t)(s1 * s2);
+    }
+
+    // --- workspace map
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    g.o_wkeys = take(n * c.key_bytes);
+    if (values) g.o_wvals = take(n * 4);
+    g.o_samp = take(sm * c.samp_bytes);
+    g.o_samp_sorted = take(sm * c.samp_bytes);
+    if (g.samp_global) g.o_samp_tmp = take(sm * c.samp_bytes);
+    g.o_counts = take(sm * 4);
+    g.o_offs = take(sm * 4);
+    if (g.scan_large) g.o_partial = take((size_t)g.scan_nrb * s1 * 4);
+    g.o_buckets1 = take(s1 * 8);
+    if (g.levels == 2) {
+        g.o_tileoff2 = take((s1 + 1) * 4);
+        const size_t sm2 = (size_t)g.tiles2max * s2;
+        g.o_samp2 = take(sm2 * c.samp_bytes);
+        g.o_samp2_sorted = take(sm2 * c.samp_bytes);
+        g.o_counts2 = take(sm2 * 4);
+        g.o_offs2 = take(sm2 * 4);
+        g.o_final = take((size_t)g.final_buckets * 8);
+    } else {
+        g.o_final = g.o_buckets1;
+    }
+    g.total = off;
+    return DSORT_OK;
+}
+
+}  // namespace dsort
+
+// ---------------------------------------------------------------------------------- C ABI
+
+using dsort::Geom;
+
+struct dsort_plan_s {
+    uint32_t magic;
+    int key_type;
+    int values;
+    uint64_t max_items;
+    uint64_t max_segments;
+    dsort_tuning_t tuning;
+    size_t workspace;
+    Geom last;  // geometry cache of the last n
+};
+
+static constexpr uint32_t kMagic = 0x44534f52u;  // "DSOR"
+
+static bool plan_ok(const dsort_plan_s *p) { return p && p->magic == kMagic; }
+
+static int geom_for(dsort_plan_s *p, uint64_t n, const Geom **out) {
+    if (p->last.n != n || p->last.levels == -2) {
+        Geom g;
+        int rc = dsort::make_geom(p->key_type, p->values != 0, n, p->tuning, g);
+        if (rc != DSORT_OK) return rc;
+        p->last = g;
+    }
+    *out = &p->last;
+    return DSORT_OK;
+}
+
+extern "C" {
+
+int dsort_plan(dsort_plan_t *out, int key_type, int with_values, uint64_t max_items,
+               uint64_t max_segments, const dsort_tuning_t *tuning, size_t *workspace_bytes) {
+    if (!out || !workspace_bytes) return DSORT_E_INVALID;
+    *out = nullptr;
+    if (key_type != DSORT_U32 && key_type != DSORT_U64 && key_type != DSORT_F32)
+        return DSORT_E_INVALID;
+    if (with_values != 0 && with_values != 1) return DSORT_E_INVALID;
+    if (max_items > dsort::kMaxItems) return DSORT_E_INVALID;
+    dsort_tuning_t tu{};
+    if (tuning) tu = *tuning;
+    // The workspace must serve every n <= max_items.  The geometry is piecewise in n: on each
+    // interval where (levels, s1, s2, sample-sort and scan variants) stay fixed, every buffer
+    // grows with n, and these pieces never recur once left (s1, s2 and the level count only
+    // grow with n).  So the largest footprint is at the right end of some piece; walk the
+    // pieces, finding each right end by bisection.
+    size_t ws = 256;
+    if (max_items >= 2) {
+        auto key = [](const Geom &h) {
+            return ((uint64_t)(h.levels + 1) << 56) ^ ((uint64_t)h.s1 << 36) ^
+                   ((uint64_t)h.s2 << 12) ^ ((uint64_t)h.samp_global << 1) ^
+                   (uint64_t)h.scan_large;
+        };
+        uint64_t lo = 2;
+        while (lo <= max_items) {
+            Geom h;
+            if (dsort::make_geom(key_type, with_values != 0, lo, tu, h) != DSORT_OK)
+                return DSORT_E_UNSUPPORTED;
+            const uint64_t k0 = key(h);
+            uint64_t a = lo, b = max_items;
+            while (a < b) {
+                const uint64_t mid = a + (b - a + 1) / 2;
+                Geom t;
+                if (dsort::make_geom(key_type, with_values != 0, mid, tu, t) == DSORT_OK &&
+                    key(t) == k0)
+                    a = mid;
+                else
+                    b = mid - 1;
+            }
+            Geom e;
+            dsort::make_geom(key_type, with_values != 0, a, tu, e);
+            if (e.total > ws) ws = e.total;
+            lo = a + 1;
+        }
+    }
+    dsort_plan_s *p = new (std::nothrow) dsort_plan_s{};
+    if (!p) return DSORT_E_NOMEM;
+    p->magic = kMagic;
+    p->key_type = key_type;
+    p->values = with_values;
+    p->max_items = max_items;
+    p->max_segments = max_segments;
+    p->tuning = tu;
+    p->workspace = ws;
+    p->last.levels = -2;
+    *out = p;
+    *workspace_bytes = ws;
+    return DSORT_OK;
+}
+
+int dsort_plan_destroy(dsort_plan_t plan) {
+    if (!plan) return DSORT_OK;
+    if (!plan_ok(plan)) return DSORT_E_INVALID;
+    plan->magic = 0;
+    delete plan;
+    return DSORT_OK;
+}
+
+const char *dsort_strerror(int status) {
+    switch (status) {
+        case DSORT_OK: return "success";
+        case DSORT_E_INVALID: return "invalid argument";
+        case DSORT_E_UNSUPPORTED: return "unsupported request (no feasible level plan)";
+        case DSORT_E_NOMEM: return "out of host memory";
+        case DSORT_E_HIP: return "HIP runtime error";
+        case DSORT_E_CAPACITY: return "request exceeds capacity";
+        case DSORT_E_TICKET: return "unknown ticket";
+        default: return "unknown status";
+    }
+}
+
+int dsort_plan_geometry(dsort_plan_t plan, uint64_t n, dsort_geometry_t *out) {
+    if (!plan_ok(plan) || !out) return DSORT_E_INVALID;
+    if (n > plan->max_items) return DSORT_E_INVALID;
+    const Geom *g = nullptr;
+    int rc = geom_for(plan, n, &g);
+    if (rc != DSORT_OK) return rc;
+    memset(out, 0, sizeof(*out));
+    out->n = n;
+    out->levels = g->levels < 0 ? 0 : (uint32_t)g->levels;
+    out->sublist_len = g->L1;
+    out->samples = g->s1;
+    out->sublists = g->m1;
+    out->sublist_len2 = g->L2;
+    out->samples2 = g->s2;
+    out->max_tiles2 = g->tiles2max;
+    out->bucket_capacity = g->caps.final_cap;
+    out->bucket_bound = g->beta1;
+    out->sample_bytes = g->caps.samp_bytes;
+    out->sample_sort_global = g->samp_global ? 1u : 0u;
+    out->off_status = g->o_status;
+    out->off_samples = g->o_samp;
+    out->off_sorted_samples = g->o_samp_sorted;
+    out->off_counts = g->o_counts;
+    out->off_offsets = g->o_offs;
+    out->off_buckets = g->o_buckets1;
+    out->workspace_bytes = g->total;
+    return DSORT_OK;
+}
+
+static int sort_common(dsort_plan_t plan, void *d_keys, uint32_t *d_vals, uint64_t n,
+                       void *d_ws, void *stream, bool with_values) {
+    if (!plan_ok(plan)) return DSORT_E_INVALID;
+    if ((plan->values != 0) != with_values) return DSORT_E_INVALID;
+    if (n > plan->max_items) return DSORT_E_INVALID;
+    if (n <= 1) return DSORT_OK;
+    if (!d_keys || !d_ws || (with_values && !d_vals)) return DSORT_E_INVALID;
+    if (((uintptr_t)d_ws & 255) != 0) return DSORT_E_INVALID;
+    if (((uintptr_t)d_keys & (plan->key_type == DSORT_U64 ? 7 : 3)) != 0) return DSORT_E_INVALID;
+    if (with_values && ((uintptr_t)d_vals & 3) != 0) return DSORT_E_INVALID;
+    const Geom *g = nullptr;
+    int rc = geom_for(plan, n, &g);
+    if (rc != DSORT_OK) return rc;
+    if (g->total > plan->workspace) return DSORT_E_CAPACITY;
+    return dsort::run_pipeline(*g, d_keys, d_vals, d_ws, stream);
+}
+
+int dsort_keys(dsort_plan_t plan, void *d_keys, uint64_t n, void *d_workspace, void *stream) {
+    return sort_common(plan, d_keys, nullptr, n, d_workspace, stream, false);
+}
+
+int dsort_pairs(dsort_plan_t plan, void *d_keys, uint32_t *d_values, uint64_t n,
+                void *d_workspace, void *stream) {
+    return sort_common(plan, d_keys, d_values, n, d_workspace, stream, true);
+}
+
+}  // extern "C"

@@ -1,0 +1,275 @@
+"""GPU parity: the HIP pipeline (called through the C ABI) against the CPU oracle.
+
+Integer work, so the bar is bit-exact everywhere: final outputs, and the level-1 intermediates
+of Algorithm 1 (sorted samples, global samples, a_ij, l_ij, bucket table) at the same (L, s).
+At full benchmark sizes the output is checked against numpy's sort (the plain definition) and,
+for key/value sorts, by properties that fix the stable result uniquely."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import from_dev, samples_from_ws, say, to_dev, ws_view
+
+pytestmark = pytest.mark.gpu
+
+KT = {np.dtype(np.uint32): 1, np.dtype(np.uint64): 2, np.dtype(np.float32): 3}
+
+
+@pytest.fixture(scope="module")
+def ds():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1002_4464_amd as d
+    d.load_library()
+    return d
+
+
+def gpu_sort(ds, keys, values=None, tuning=None, plan=None):
+    import torch
+    kt = KT[keys.dtype]
+    if plan is None:
+        plan = ds.Plan(kt, values is not None, max(keys.size, 2), tuning)
+    tk = to_dev(keys)
+    ws = plan.workspace(tk.device)
+    if values is None:
+        plan.sort_keys(tk, ws)
+        tv = None
+    else:
+        tv = to_dev(values)
+        plan.sort_pairs(tk, tv, ws)
+    torch.cuda.synchronize()
+    geo = plan.geometry(keys.size)
+    status = int(ws_view(ws, geo.off_status, 1, np.uint32)[0])
+    assert status == 0, f"kernel status flags {status:#x}"
+    out_k = from_dev(tk, keys.dtype)
+    out_v = from_dev(tv, np.uint32) if tv is not None else None
+    return out_k, out_v, geo, ws
+
+
+def check_level1(geo, ws, tr, n):
+    """Level-1 intermediates equal the oracle's at the same (L, s)."""
+    m, s = geo.sublists, geo.samples
+    assert (m, s, geo.sublist_len) == (tr.m, tr.s, tr.L)
+    sk, sp = samples_from_ws(ws, geo.off_sorted_samples, m * s, geo.sample_bytes)
+    assert (sk == tr.sample_key).all(), "sorted sample keys (Step 4)"
+    assert (sp == tr.sample_pos).all(), "sorted sample positions (Step 4)"
+    counts = ws_view(ws, geo.off_counts, m * s, np.uint32).reshape(m, s)
+    assert (counts == tr.count).all(), "a_ij (Step 6)"
+    offs = ws_view(ws, geo.off_offsets, m * s, np.uint32).reshape(m, s)
+    assert (offs == tr.offset).all(), "l_ij (Step 7)"
+    b = ws_view(ws, geo.off_buckets, 2 * s, np.uint32).reshape(s, 2).astype(np.int64)
+    begin = tr.offset[0].astype(np.int64)
+    real = np.clip(n - begin, 0, tr.bucket_size.astype(np.int64))
+    assert (b[:, 0] == begin).all(), "bucket starts (Step 8)"
+    assert (b[:, 1] == real).all(), "bucket sizes (Step 8)"
+
+
+# ------------------------------------------------------------------ small, one tile
+
+@pytest.mark.parametrize("n", [2, 3, 17, 64, 1000, 4097, 32767, 32768])
+def test_single_tile_u32(ds, n):
+    say(f"single tile u32 n={n}")
+    keys = synth.uniform_u32(n, 100 + n) % np.uint32(max(2, n // 3))
+    out, _, geo, _ = gpu_sort(ds, keys)
+    assert geo.levels == 0
+    assert (out == oracle.stable_sort(keys)[0]).all()
+
+
+@pytest.mark.parametrize("kind", ["u32_pairs", "u64", "u64_pairs", "f32"])
+def test_single_tile_types(ds, kind):
+    say(f"single tile {kind}")
+    n = 5000
+    vals = synth.draws32(7, n)
+    if kind.startswith("u64"):
+        keys = synth.zipf_u64(n, 3, distinct=300)
+    elif kind == "f32":
+        keys = synth.normal_f32_segments([n], 4)
+    else:
+        keys = synth.uniform_u32(n, 5) % np.uint32(50)
+    pv = vals if kind.endswith("pairs") else None
+    out_k, out_v, geo, _ = gpu_sort(ds, keys, pv)
+    ek, ev = oracle.stable_sort(keys, pv)
+    assert geo.levels == 0
+    assert (out_k.view(np.uint8) == ek.view(np.uint8)).all()
+    if pv is not None:
+        assert (out_v == ev).all()
+
+
+# ------------------------------------------------------------------ one level, intermediates
+
+def test_c1_uniform_2p20(ds):
+    """2^20 uniform uint32 keys (seed 1), automatic plan: output and intermediates."""
+    say("C1 2^20 uniform u32")
+    keys = synth.uniform_u32(1 << 20, 1)
+    out, _, geo, ws = gpu_sort(ds, keys)
+    assert geo.levels == 1
+    ok, _, tr = oracle.dss(keys, geo.sublist_len, geo.samples, trace=True)
+    assert (out == ok).all()
+    check_level1(geo, ws, tr, keys.size)
+
+
+CASES = [
+    # (n, L, s)
+    (50_037, 1024, 32),
+    (65_536, 2048, 64),
+    (9_999, 256, 8),
+    (100_003, 1024, 256),  # m*s > one workgroup: Step 4 by chunk sorts + merge rounds
+    (16_385, 16384, 64),   # last sublist holds a single real item, the rest pads
+]
+
+
+@pytest.mark.parametrize("dist", sorted(synth.DISTRIBUTIONS_U32))
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"n{c[0]}_L{c[1]}_s{c[2]}")
+def test_one_level_intermediates(ds, dist, case):
+    n, L, s = case
+    say(f"one level {dist} n={n} L={L} s={s}")
+    keys = synth.make_u32(dist, n, 21)
+    tu = ds.Tuning(L, s, 0, 0, 1)
+    out, _, geo, ws = gpu_sort(ds, keys, tuning=tu)
+    assert geo.levels == 1
+    ok, _, tr = oracle.dss(keys, L, s, trace=True)
+    assert (out == ok).all()
+    check_level1(geo, ws, tr, n)
+
+
+def test_pairs_u32_stable_intermediates(ds):
+    n = 300_001
+    say(f"pairs u32 n={n}")
+    keys = synth.uniform_u32(n, 31) % np.uint32(1000)
+    vals = synth.index_values(n)
+    out_k, out_v, geo, ws = gpu_sort(ds, keys, vals)
+    ok, ov, tr = oracle.dss(keys, geo.sublist_len, geo.samples, values=vals, trace=True)
+    assert (out_k == ok).all() and (out_v == ov).all()
+    check_level1(geo, ws, tr, n)
+
+
+def test_f32_keys_intermediates(ds):
+    sizes = [70_000]
+    say("f32 keys n=70000 + specials")
+    x = synth.normal_f32_segments(sizes, 41)
+    x[::997] = np.float32(np.inf)
+    x[5::1013] = np.float32(-np.inf)
+    x[7::1021] = np.float32(np.nan)
+    x[9::1031] = -np.float32(np.nan)
+    out, _, geo, ws = gpu_sort(ds, x, tuning=ds.Tuning(2048, 32, 0, 0, 1))
+    ok, _, tr = oracle.dss(x, 2048, 32, trace=True)
+    assert (out.view(np.uint32) == ok.view(np.uint32)).all()
+    check_level1(geo, ws, tr, x.size)
+
+
+def test_f32_pairs(ds):
+    n = 123_457
+    say(f"f32 pairs n={n}")
+    x = synth.normal_f32_segments([n], 43)
+    vals = synth.index_values(n)
+    out_k, out_v, geo, ws = gpu_sort(ds, x, vals)
+    ok, ov, tr = oracle.dss(x, geo.sublist_len, geo.samples, values=vals, trace=True)
+    assert (out_k.view(np.uint32) == ok.view(np.uint32)).all() and (out_v == ov).all()
+    check_level1(geo, ws, tr, n)
+
+
+@pytest.mark.parametrize("pairs", [False, True])
+def test_u64_intermediates(ds, pairs):
+    n = 200_003
+    say(f"u64 pairs={pairs} n={n}")
+    keys = synth.zipf_u64(n, 51, distinct=5000)
+    vals = synth.index_values(n) if pairs else None
+    out_k, out_v, geo, ws = gpu_sort(ds, keys, vals)
+    ok, ov, tr = oracle.dss(keys, geo.sublist_len, geo.samples, values=vals, trace=True)
+    assert (out_k == ok).all()
+    if pairs:
+        assert (out_v == ov).all()
+    check_level1(geo, ws, tr, n)
+
+
+def test_u64_pairs_global_sample_sort(ds):
+    n = 400_000
+    say(f"u64 pairs global sample sort n={n}")
+    keys = synth.zipf_u64(n, 53, distinct=1000)
+    vals = synth.index_values(n)
+    tu = ds.Tuning(1024, 256, 0, 0, 1)
+    out_k, out_v, geo, ws = gpu_sort(ds, keys, vals, tuning=tu)
+    assert geo.sample_sort_global
+    ok, ov, tr = oracle.dss(keys, 1024, 256, values=vals, trace=True)
+    assert (out_k == ok).all() and (out_v == ov).all()
+    check_level1(geo, ws, tr, n)
+
+
+# ------------------------------------------------------------------ two levels
+
+@pytest.mark.parametrize("dist", ["uniform", "equal", "sorted", "staggered"])
+def test_two_level_forced(ds, dist):
+    n = 200_000 + 7
+    say(f"two level forced {dist} n={n}")
+    keys = synth.make_u32(dist, n, 61)
+    tu = ds.Tuning(2048, 16, 1024, 0, 2)
+    out, _, geo, ws = gpu_sort(ds, keys, tuning=tu)
+    assert geo.levels == 2
+    ok, _, tr = oracle.dss(keys, 2048, 16, trace=True)
+    assert (out == ok).all()
+    check_level1(geo, ws, tr, n)
+
+
+def test_two_level_pairs_forced(ds):
+    n = 150_001
+    say(f"two level pairs n={n}")
+    keys = synth.uniform_u32(n, 63) % np.uint32(77)
+    vals = synth.index_values(n)
+    tu = ds.Tuning(1024, 16, 512, 0, 2)
+    out_k, out_v, geo, ws = gpu_sort(ds, keys, vals, tuning=tu)
+    assert geo.levels == 2
+    ok, ov, tr = oracle.dss(keys, 1024, 16, values=vals, trace=True)
+    assert (out_k == ok).all() and (out_v == ov).all()
+    check_level1(geo, ws, tr, n)
+
+
+def test_two_level_auto_2p24(ds):
+    n = 1 << 24
+    say(f"two level auto u32 n={n}")
+    keys = synth.uniform_u32(n, 65)
+    out, _, geo, ws = gpu_sort(ds, keys)
+    assert geo.levels == 2
+    ok, _, tr = oracle.dss(keys, geo.sublist_len, geo.samples, trace=True)
+    assert (out == ok).all()
+    check_level1(geo, ws, tr, n)
+
+
+# ------------------------------------------------------------------ benchmark sizes
+
+@pytest.mark.parametrize("dist", sorted(synth.DISTRIBUTIONS_U32))
+def test_2p26_distributions(ds, dist):
+    """2^26 uint32 keys of each distribution; run twice, bit-identical (determinism)."""
+    n = 1 << 26
+    say(f"2^26 {dist}")
+    keys = synth.make_u32(dist, n, {"uniform": 2, "gaussian": 3, "bucket": 4, "staggered": 5,
+                                    "sorted": 6, "equal": 7}[dist])
+    out, _, geo, ws = gpu_sort(ds, keys)
+    assert (out == np.sort(keys)).all()
+    out2, _, _, _ = gpu_sort(ds, keys)
+    assert (out2 == out).all()
+
+
+def test_2p28_uniform(ds):
+    n = 1 << 28
+    say("2^28 uniform u32")
+    keys = synth.uniform_u32(n, 8)
+    out, _, geo, ws = gpu_sort(ds, keys)
+    ref = np.sort(keys)
+    assert (out == ref).all()
+
+
+def test_2p27_u64_pairs_zipf(ds):
+    """2^27 (uint64 key, uint32 value = input index), Zipf(1.1) keys: the output is the
+    stable sort iff keys are non-decreasing, values are a permutation that maps the input keys
+    onto the output keys, and values increase inside every run of equal keys."""
+    n = 1 << 27
+    say("2^27 u64 pairs zipf")
+    keys = synth.zipf_u64(n, 10)
+    vals = synth.index_values(n)
+    out_k, out_v, geo, ws = gpu_sort(ds, keys, vals)
+    assert (out_k[1:] >= out_k[:-1]).all()
+    assert (keys[out_v] == out_k).all()
+    assert (np.bincount(out_v, minlength=n) == 1).all()
+    same = out_k[1:] == out_k[:-1]
+    assert (out_v[1:][same] > out_v[:-1][same]).all()
