@@ -120,6 +120,19 @@ typedef struct {
 
 int dsort_plan_geometry(dsort_plan_t plan, uint64_t n, dsort_geometry_t *out);
 
+/* Per-kernel timing, for profiling.  dsort_set_timing(plan, 1) clears the record and makes
+ * every later sorting call on `plan` bracket each kernel launch with two HIP events recorded
+ * on the call's stream (events are created on first use and owned by the plan); 0 stops
+ * recording.  After synchronising the stream(s) of the recorded calls, dsort_stage_times()
+ * averages the recorded launches per stage: it writes up to `capacity` entries of `names`
+ * (static strings, e.g. "s123_local_sort", "s9_bucket_sort"), `avg_ms` (mean milliseconds per
+ * launch) and `launches` (launch count; each may be NULL), and the number of stages to *count.
+ * Errors: DSORT_E_INVALID (bad plan, NULL count), DSORT_E_HIP (event query failed, e.g. the
+ * work has not completed). */
+int dsort_set_timing(dsort_plan_t plan, int enable);
+int dsort_stage_times(dsort_plan_t plan, const char **names, float *avg_ms, uint32_t *launches,
+                      int capacity, int *count);
+
 #ifdef __cplusplus
 }
 #endif

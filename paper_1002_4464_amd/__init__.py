@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libdsort.so")
 
 EXPORTED_SYMBOLS = (
     "dsort_plan", "dsort_keys", "dsort_pairs", "dsort_plan_destroy", "dsort_strerror",
-    "dsort_plan_geometry",
+    "dsort_plan_geometry", "dsort_set_timing", "dsort_stage_times",
 )
 
 
@@ -79,6 +79,12 @@ def load_library(path: str = LIB_PATH):
     lib.dsort_strerror.restype = ctypes.c_char_p
     lib.dsort_plan_geometry.argtypes = [P, U64_, ctypes.POINTER(_Geometry)]
     lib.dsort_plan_geometry.restype = I
+    lib.dsort_set_timing.argtypes = [P, I]
+    lib.dsort_set_timing.restype = I
+    lib.dsort_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_char_p),
+                                      ctypes.POINTER(ctypes.c_float),
+                                      ctypes.POINTER(ctypes.c_uint32), I, ctypes.POINTER(I)]
+    lib.dsort_stage_times.restype = I
     _lib = lib
     return lib
 
@@ -146,6 +152,22 @@ class Plan:
         _check(self._lib.dsort_plan_geometry(self._h, int(n), ctypes.byref(g)),
                "dsort_plan_geometry")
         return Geometry(*[getattr(g, f) for f, _ in _Geometry._fields_])
+
+    def set_timing(self, enable: bool):
+        """Bracket every kernel launch of later calls with HIP events (clears the record)."""
+        _check(self._lib.dsort_set_timing(self._h, int(bool(enable))), "dsort_set_timing")
+
+    def stage_times(self) -> dict:
+        """{stage name: (mean ms per launch, launches)} over the recorded calls; call after
+        synchronising the stream the calls ran on."""
+        cap = 64
+        names = (ctypes.c_char_p * cap)()
+        ms = (ctypes.c_float * cap)()
+        cnt = (ctypes.c_uint32 * cap)()
+        c = ctypes.c_int()
+        _check(self._lib.dsort_stage_times(self._h, names, ms, cnt, cap, ctypes.byref(c)),
+               "dsort_stage_times")
+        return {names[i].decode(): (float(ms[i]), int(cnt[i])) for i in range(min(c.value, cap))}
 
     def workspace(self, device):
         """A workspace tensor (uint8, plan.workspace_bytes) on ``device``, cached."""

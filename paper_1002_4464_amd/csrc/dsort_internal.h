@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/dsort.h"
 
 namespace dsort {
@@ -56,8 +58,29 @@ struct Geom {
 // Computes the geometry for n items.  Returns DSORT_OK or DSORT_E_UNSUPPORTED.
 int make_geom(int key_type, bool values, uint64_t n, const dsort_tuning_t &tuning, Geom &g);
 
-// Enqueues the whole pipeline (kernels.hip).  Pointers are device pointers.
-int run_pipeline(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, void *stream);
+// Optional per-kernel timing: every launch of a sorting call is bracketed by two HIP events
+// (hipEvent_t stored as void*) recorded on the call's stream.
+struct StageRec {
+    const char *name;
+    void *ev0;
+    void *ev1;
+};
+struct Timing {
+    bool enabled = false;
+    std::vector<void *> pool;  // events, reused across resets
+    size_t used = 0;
+    std::vector<StageRec> recs;
+};
+void timing_reset(Timing &t);
+void timing_destroy(Timing &t);
+// Averages the recorded launches per stage name (in first-seen order).  Needs the stream of
+// the recorded calls to have been synchronised.  Returns DSORT_OK or DSORT_E_HIP.
+int timing_summary(Timing &t, const char **names, float *avg_ms, uint32_t *launches,
+                   int capacity, int *count);
+
+// Enqueues the whole pipeline (kernels.hip).  Pointers are device pointers; tm may be null.
+int run_pipeline(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, void *stream,
+                 Timing *tm);
 
 constexpr uint64_t kMaxItems = (1ull << 32) - (1ull << 16);
 

@@ -635,6 +635,35 @@ __global__ void k_init(uint32_t *status) {
         if (hipGetLastError() != hipSuccess) return DSORT_E_HIP; \
     } while (0)
 
+// Launch with optional timing events around it.
+#define DS_LAUNCH(NAME, KERNEL, GRID, BLOCK, ...)                                   \
+    do {                                                                            \
+        void *ev1_ = nullptr;                                                       \
+        if (tm && stage_begin(*tm, NAME, st, &ev1_) != DSORT_OK) return DSORT_E_HIP; \
+        hipLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, st, __VA_ARGS__);                \
+        if (hipGetLastError() != hipSuccess) return DSORT_E_HIP;                    \
+        if (ev1_ && hipEventRecord((hipEvent_t)ev1_, st) != hipSuccess) return DSORT_E_HIP; \
+    } while (0)
+
+void *pool_event(Timing &t) {
+    if (t.used == t.pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        t.pool.push_back((void *)e);
+    }
+    return t.pool[t.used++];
+}
+
+int stage_begin(Timing &t, const char *name, hipStream_t st, void **ev1) {
+    void *a = pool_event(t);
+    void *b = pool_event(t);
+    if (!a || !b) return DSORT_E_HIP;
+    if (hipEventRecord((hipEvent_t)a, st) != hipSuccess) return DSORT_E_HIP;
+    t.recs.push_back(StageRec{name, a, b});
+    *ev1 = b;
+    return DSORT_OK;
+}
+
 template <class K, bool V, bool F32> struct Pipeline {
     using R = Tr<K, V>;
     using SC = typename R::SC;
@@ -645,45 +674,44 @@ template <class K, bool V, bool F32> struct Pipeline {
     static constexpr int SE = sizeof(SC) >= 16 ? 8 : 16;
     static constexpr int SCAP = SE * 1024;
 
-    static int sort_samples(const Geom &g, const SC *samp, SC *sorted, SC *tmp, SegView sv,
-                            uint32_t L, uint32_t s, uint32_t G, uint32_t *status,
-                            hipStream_t st, bool global, uint32_t rounds) {
+    // Step 4 for one level.  G > 0 segments sorted one workgroup each, or (global) the single
+    // segment's m*s samples by chunk sorts plus merge rounds ending in `sorted`.
+    static int sort_samples(const SC *samp, SC *sorted, SC *tmp, SegView sv, uint32_t L,
+                            uint32_t s, uint32_t G, uint32_t total, uint32_t *status,
+                            hipStream_t st, bool global, uint32_t rounds, Timing *tm,
+                            const char *name, const char *name_merge) {
         if (!global) {
-            hipLaunchKernelGGL((k_sort_samples<SC, SE, SCAP>), dim3(G), dim3(SCAP / SE), 0, st,
-                               samp, sorted, sv, L, s, 0u, status);
-            DS_CHECK_LAUNCH();
+            DS_LAUNCH(name, (k_sort_samples<SC, SE, SCAP>), dim3(G), dim3(SCAP / SE), samp,
+                      sorted, sv, L, s, 0u, status);
             return DSORT_OK;
         }
-        const uint32_t total = g.m1 * g.s1;
         const uint32_t chunks = (total + SCAP - 1) / SCAP;
-        // ping-pong so that the last round lands in `sorted`
-        SC *x = (rounds % 2 == 0) ? sorted : tmp;
+        SC *x = (rounds % 2 == 0) ? sorted : tmp;  // the last round must land in `sorted`
         SC *y = (rounds % 2 == 0) ? tmp : sorted;
-        hipLaunchKernelGGL((k_sort_samples<SC, SE, SCAP>), dim3(chunks), dim3(SCAP / SE), 0, st,
-                           samp, x, sv, L, s, total, status);
-        DS_CHECK_LAUNCH();
+        DS_LAUNCH(name, (k_sort_samples<SC, SE, SCAP>), dim3(chunks), dim3(SCAP / SE), samp, x,
+                  sv, L, s, total, status);
         for (uint32_t run = SCAP; run < total; run <<= 1) {
-            hipLaunchKernelGGL((k_merge_round<SC, SE, SCAP>), dim3(chunks), dim3(SCAP / SE), 0,
-                               st, x, y, total, run);
-            DS_CHECK_LAUNCH();
-            SC *t = x; x = y; y = t;
+            DS_LAUNCH(name_merge, (k_merge_round<SC, SE, SCAP>), dim3(chunks), dim3(SCAP / SE),
+                      (const SC *)x, y, total, run);
+            SC *t = x;
+            x = y;
+            y = t;
         }
         return DSORT_OK;
     }
 
-    static int run(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, hipStream_t st) {
+    static int run(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, hipStream_t st,
+                   Timing *tm) {
         char *ws = (char *)d_ws;
         uint32_t *status = (uint32_t *)(ws + g.o_status);
-        hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, status);
-        DS_CHECK_LAUNCH();
+        DS_LAUNCH("init", k_init, dim3(1), dim3(64), status);
         K *keys = (K *)d_keys;
         const uint32_t n = (uint32_t)g.n;
         if (g.levels == 0) {
             TileArgs a{keys, keys, d_vals, d_vals, SegView{nullptr, nullptr, 1, n, n, 0}, 0, 0,
                        nullptr, status};
-            hipLaunchKernelGGL((k_tile<K, V, FE, FCAP, MODE_FINAL, F32, F32>), dim3(1),
-                               dim3(FCAP / FE), 0, st, a);
-            DS_CHECK_LAUNCH();
+            DS_LAUNCH("s9_bucket_sort", (k_tile<K, V, FE, FCAP, MODE_FINAL, F32, F32>), dim3(1),
+                      dim3(FCAP / FE), a);
             return DSORT_OK;
         }
         K *wkeys = (K *)(ws + g.o_wkeys);
@@ -700,47 +728,42 @@ template <class K, bool V, bool F32> struct Pipeline {
         // Steps 1-3
         {
             TileArgs a{keys, keys, d_vals, d_vals, sv1, g.L1, g.s1, samp, status};
-            hipLaunchKernelGGL((k_tile<K, V, TE, TCAP, MODE_SAMPLE, F32, false>), dim3(g.m1),
-                               dim3(g.L1 / TE), 0, st, a);
-            DS_CHECK_LAUNCH();
+            DS_LAUNCH("s123_local_sort", (k_tile<K, V, TE, TCAP, MODE_SAMPLE, F32, false>),
+                      dim3(g.m1), dim3(g.L1 / TE), a);
         }
         // Step 4
-        int rc = sort_samples(g, samp, sorted, tmp, sv1, g.L1, g.s1, 1, status, st,
-                              g.samp_global, g.samp_rounds);
+        int rc = sort_samples(samp, sorted, tmp, sv1, g.L1, g.s1, 1, g.m1 * g.s1, status, st,
+                              g.samp_global, g.samp_rounds, tm, "s4_sample_sort",
+                              "s4_sample_merge");
         if (rc) return rc;
         // Steps 5-6
-        hipLaunchKernelGGL((k_rank<K, V>), dim3(g.m1), dim3(256), 0, st, keys,
-                           (const void *)sorted, counts, sv1, g.L1, g.s1);
-        DS_CHECK_LAUNCH();
+        DS_LAUNCH("s56_rank", (k_rank<K, V>), dim3(g.m1), dim3(256), (const K *)keys,
+                  (const void *)sorted, counts, sv1, g.L1, g.s1);
         // Step 7
         if (!g.scan_large) {
-            hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(256), 0, st, counts, offs, sv1, g.L1,
-                               g.s1, buckets1, tileoff2, g.L2);
-            DS_CHECK_LAUNCH();
+            DS_LAUNCH("s7_scan", k_scan_small, dim3(1), dim3(256), (const uint32_t *)counts,
+                      offs, sv1, g.L1, g.s1, buckets1, tileoff2, g.L2);
         } else {
             uint32_t *partial = (uint32_t *)(ws + g.o_partial);
-            hipLaunchKernelGGL(k_scan_partial, dim3(g.scan_nrb), dim3(256), 0, st, counts, partial,
-                               g.m1, g.s1, g.scan_rb);
-            DS_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_scan_mid, dim3(1), dim3(256), 0, st, partial, g.scan_nrb, g.s1,
-                               n, buckets1, tileoff2, g.L2);
-            DS_CHECK_LAUNCH();
-            hipLaunchKernelGGL(k_scan_apply, dim3(g.scan_nrb), dim3(256), 0, st, counts, partial,
-                               offs, g.m1, g.s1, g.scan_rb);
-            DS_CHECK_LAUNCH();
+            DS_LAUNCH("s7_scan_colsum", k_scan_partial, dim3(g.scan_nrb), dim3(256),
+                      (const uint32_t *)counts, partial, g.m1, g.s1, g.scan_rb);
+            DS_LAUNCH("s7_scan_mid", k_scan_mid, dim3(1), dim3(256), partial, g.scan_nrb, g.s1,
+                      n, buckets1, tileoff2, g.L2);
+            DS_LAUNCH("s7_scan_update", k_scan_apply, dim3(g.scan_nrb), dim3(256),
+                      (const uint32_t *)counts, (const uint32_t *)partial, offs, g.m1, g.s1,
+                      g.scan_rb);
         }
         // Step 8
-        hipLaunchKernelGGL((k_relocate<K, V>), dim3(g.m1), dim3(256), 0, st, keys, wkeys,
-                           d_vals, wvals, counts, offs, sv1, g.L1, g.s1);
-        DS_CHECK_LAUNCH();
+        DS_LAUNCH("s8_relocate", (k_relocate<K, V>), dim3(g.m1), dim3(256), (const K *)keys,
+                  wkeys, (const uint32_t *)d_vals, wvals, (const uint32_t *)counts,
+                  (const uint32_t *)offs, sv1, g.L1, g.s1);
 
         if (g.levels == 1) {
             // Step 9: every bucket in one workgroup, from the relocated copy back into keys.
-            TileArgs a{wkeys, keys, wvals, d_vals, SegView{buckets1, nullptr, g.s1, 0, n, 0}, 0, 0,
-                       nullptr, status};
-            hipLaunchKernelGGL((k_tile<K, V, FE, FCAP, MODE_FINAL, false, F32>), dim3(g.s1),
-                               dim3(FCAP / FE), 0, st, a);
-            DS_CHECK_LAUNCH();
+            TileArgs a{wkeys, keys, wvals, d_vals, SegView{buckets1, nullptr, g.s1, 0, n, 0}, 0,
+                       0, nullptr, status};
+            DS_LAUNCH("s9_bucket_sort", (k_tile<K, V, FE, FCAP, MODE_FINAL, false, F32>),
+                      dim3(g.s1), dim3(FCAP / FE), a);
             return DSORT_OK;
         }
 
@@ -753,27 +776,24 @@ template <class K, bool V, bool F32> struct Pipeline {
         uint2 *finals = (uint2 *)(ws + g.o_final);
         {
             TileArgs a{wkeys, wkeys, wvals, wvals, sv2, g.L2, g.s2, samp2, status};
-            hipLaunchKernelGGL((k_tile<K, V, TE, TCAP, MODE_SAMPLE, false, false>),
-                               dim3(g.tiles2max), dim3(g.L2 / TE), 0, st, a);
-            DS_CHECK_LAUNCH();
+            DS_LAUNCH("l2_s123_local_sort", (k_tile<K, V, TE, TCAP, MODE_SAMPLE, false, false>),
+                      dim3(g.tiles2max), dim3(g.L2 / TE), a);
         }
-        rc = sort_samples(g, samp2, sorted2, nullptr, sv2, g.L2, g.s2, g.s1, status, st, false, 0);
+        rc = sort_samples(samp2, sorted2, nullptr, sv2, g.L2, g.s2, g.s1, 0, status, st, false, 0,
+                          tm, "l2_s4_sample_sort", "l2_s4_sample_merge");
         if (rc) return rc;
-        hipLaunchKernelGGL((k_rank<K, V>), dim3(g.tiles2max), dim3(256), 0, st, wkeys,
-                           (const void *)sorted2, counts2, sv2, g.L2, g.s2);
-        DS_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_scan_small, dim3(g.s1), dim3(256), 0, st, counts2, offs2, sv2, g.L2,
-                           g.s2, finals, (uint32_t *)nullptr, 0u);
-        DS_CHECK_LAUNCH();
-        hipLaunchKernelGGL((k_relocate<K, V>), dim3(g.tiles2max), dim3(256), 0, st, wkeys, keys,
-                           wvals, d_vals, counts2, offs2, sv2, g.L2, g.s2);
-        DS_CHECK_LAUNCH();
+        DS_LAUNCH("l2_s56_rank", (k_rank<K, V>), dim3(g.tiles2max), dim3(256), (const K *)wkeys,
+                  (const void *)sorted2, counts2, sv2, g.L2, g.s2);
+        DS_LAUNCH("l2_s7_scan", k_scan_small, dim3(g.s1), dim3(256), (const uint32_t *)counts2,
+                  offs2, sv2, g.L2, g.s2, finals, (uint32_t *)nullptr, 0u);
+        DS_LAUNCH("l2_s8_relocate", (k_relocate<K, V>), dim3(g.tiles2max), dim3(256),
+                  (const K *)wkeys, keys, (const uint32_t *)wvals, d_vals,
+                  (const uint32_t *)counts2, (const uint32_t *)offs2, sv2, g.L2, g.s2);
         {
-            TileArgs a{keys, keys, d_vals, d_vals,
-                       SegView{finals, nullptr, g.final_buckets, 0, n, 0}, 0, 0, nullptr, status};
-            hipLaunchKernelGGL((k_tile<K, V, FE, FCAP, MODE_FINAL, false, F32>),
-                               dim3(g.final_buckets), dim3(FCAP / FE), 0, st, a);
-            DS_CHECK_LAUNCH();
+            TileArgs a{keys, keys, d_vals, d_vals, SegView{finals, nullptr, g.final_buckets, 0, n, 0},
+                       0, 0, nullptr, status};
+            DS_LAUNCH("s9_bucket_sort", (k_tile<K, V, FE, FCAP, MODE_FINAL, false, F32>),
+                      dim3(g.final_buckets), dim3(FCAP / FE), a);
         }
         return DSORT_OK;
     }
@@ -781,20 +801,63 @@ template <class K, bool V, bool F32> struct Pipeline {
 
 }  // namespace
 
-int run_pipeline(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, void *stream) {
+void timing_reset(Timing &t) {
+    t.used = 0;
+    t.recs.clear();
+}
+
+void timing_destroy(Timing &t) {
+    for (void *e : t.pool) hipEventDestroy((hipEvent_t)e);
+    t.pool.clear();
+    t.recs.clear();
+    t.used = 0;
+}
+
+int timing_summary(Timing &t, const char **names, float *avg_ms, uint32_t *launches,
+                   int capacity, int *count) {
+    std::vector<const char *> nm;
+    std::vector<double> sum;
+    std::vector<uint32_t> cnt;
+    for (const StageRec &r : t.recs) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, (hipEvent_t)r.ev0, (hipEvent_t)r.ev1) != hipSuccess)
+            return DSORT_E_HIP;
+        size_t k = 0;
+        while (k < nm.size() && nm[k] != r.name) ++k;
+        if (k == nm.size()) {
+            nm.push_back(r.name);
+            sum.push_back(0.0);
+            cnt.push_back(0);
+        }
+        sum[k] += ms;
+        cnt[k] += 1;
+    }
+    const int c = (int)nm.size();
+    for (int k = 0; k < c && k < capacity; ++k) {
+        if (names) names[k] = nm[k];
+        if (avg_ms) avg_ms[k] = (float)(sum[k] / cnt[k]);
+        if (launches) launches[k] = cnt[k];
+    }
+    *count = c;
+    return DSORT_OK;
+}
+
+int run_pipeline(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, void *stream,
+                 Timing *tm) {
     hipStream_t st = (hipStream_t)stream;
     if (g.levels < 0) return DSORT_OK;
     if (g.n > 0xFFFFFFFFull) return DSORT_E_INVALID;
+    if (tm && !tm->enabled) tm = nullptr;
     switch (g.key_type) {
         case DSORT_U32:
-            return g.values ? Pipeline<uint32_t, true, false>::run(g, d_keys, d_vals, d_ws, st)
-                            : Pipeline<uint32_t, false, false>::run(g, d_keys, d_vals, d_ws, st);
+            return g.values ? Pipeline<uint32_t, true, false>::run(g, d_keys, d_vals, d_ws, st, tm)
+                            : Pipeline<uint32_t, false, false>::run(g, d_keys, d_vals, d_ws, st, tm);
         case DSORT_F32:
-            return g.values ? Pipeline<uint32_t, true, true>::run(g, d_keys, d_vals, d_ws, st)
-                            : Pipeline<uint32_t, false, true>::run(g, d_keys, d_vals, d_ws, st);
+            return g.values ? Pipeline<uint32_t, true, true>::run(g, d_keys, d_vals, d_ws, st, tm)
+                            : Pipeline<uint32_t, false, true>::run(g, d_keys, d_vals, d_ws, st, tm);
         case DSORT_U64:
-            return g.values ? Pipeline<uint64_t, true, false>::run(g, d_keys, d_vals, d_ws, st)
-                            : Pipeline<uint64_t, false, false>::run(g, d_keys, d_vals, d_ws, st);
+            return g.values ? Pipeline<uint64_t, true, false>::run(g, d_keys, d_vals, d_ws, st, tm)
+                            : Pipeline<uint64_t, false, false>::run(g, d_keys, d_vals, d_ws, st, tm);
         default:
             return DSORT_E_INVALID;
     }

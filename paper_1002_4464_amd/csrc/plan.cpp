@@ -209,6 +209,7 @@ struct dsort_plan_s {
     dsort_tuning_t tuning;
     size_t workspace;
     Geom last;  // geometry cache of the last n
+    dsort::Timing timing;
 };
 
 static constexpr uint32_t kMagic = 0x44534f52u;  // "DSOR"
@@ -291,6 +292,7 @@ int dsort_plan_destroy(dsort_plan_t plan) {
     if (!plan) return DSORT_OK;
     if (!plan_ok(plan)) return DSORT_E_INVALID;
     plan->magic = 0;
+    dsort::timing_destroy(plan->timing);
     delete plan;
     return DSORT_OK;
 }
@@ -351,7 +353,20 @@ static int sort_common(dsort_plan_t plan, void *d_keys, uint32_t *d_vals, uint64
     int rc = geom_for(plan, n, &g);
     if (rc != DSORT_OK) return rc;
     if (g->total > plan->workspace) return DSORT_E_CAPACITY;
-    return dsort::run_pipeline(*g, d_keys, d_vals, d_ws, stream);
+    return dsort::run_pipeline(*g, d_keys, d_vals, d_ws, stream, &plan->timing);
+}
+
+int dsort_set_timing(dsort_plan_t plan, int enable) {
+    if (!plan_ok(plan)) return DSORT_E_INVALID;
+    plan->timing.enabled = enable != 0;
+    dsort::timing_reset(plan->timing);
+    return DSORT_OK;
+}
+
+int dsort_stage_times(dsort_plan_t plan, const char **names, float *avg_ms, uint32_t *launches,
+                      int capacity, int *count) {
+    if (!plan_ok(plan) || !count || capacity < 0) return DSORT_E_INVALID;
+    return dsort::timing_summary(plan->timing, names, avg_ms, launches, capacity, count);
 }
 
 int dsort_keys(dsort_plan_t plan, void *d_keys, uint64_t n, void *d_workspace, void *stream) {
