@@ -92,6 +92,11 @@ int dsort_plan_destroy(dsort_plan_t plan);
 /* Static description of the string for a status code (never NULL). */
 const char *dsort_strerror(int status);
 
+/* Details of the last DSORT_E_HIP failure on the calling thread: the pipeline stage whose launch
+ * failed and the HIP error name and text ("" if none).  Valid until the thread's next failing
+ * call. */
+const char *dsort_last_error(void);
+
 /* Geometry the plan uses for a call with `n` items, and where the intermediates of the first
  * level live inside the workspace after such a call (byte offsets from d_workspace).
  * levels: 0 = the whole input fits one workgroup tile and is sorted directly;
@@ -114,7 +119,7 @@ typedef struct {
     uint64_t off_sorted_samples;  /* level-1 samples after Step 4 */
     uint64_t off_counts;          /* a_ij (Step 6) */
     uint64_t off_offsets;         /* l_ij (Step 7) */
-    uint64_t off_buckets;         /* level-1 buckets as {uint32 begin, uint32 size} (Step 8) */
+    uint64_t off_buckets;         /* level-1 buckets as uint32 {begin, size, first piece, pieces} */
     uint64_t workspace_bytes;     /* bytes this n needs (<= the plan's workspace size) */
 } dsort_geometry_t;
 

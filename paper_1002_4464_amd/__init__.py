@@ -24,14 +24,17 @@ LIB_PATH = os.path.join(_HERE, "libdsort.so")
 
 EXPORTED_SYMBOLS = (
     "dsort_plan", "dsort_keys", "dsort_pairs", "dsort_plan_destroy", "dsort_strerror",
-    "dsort_plan_geometry", "dsort_set_timing", "dsort_stage_times",
+    "dsort_plan_geometry", "dsort_set_timing", "dsort_stage_times", "dsort_last_error",
 )
 
 
 class DsortError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         self.status = status
-        super().__init__(f"{what}: {strerror(status)} ({status})" if what else strerror(status))
+        msg = f"{what}: {strerror(status)} ({status})" if what else strerror(status)
+        if status == E_HIP:
+            msg += f" [{load_library().dsort_last_error().decode()}]"
+        super().__init__(msg)
 
 
 class Tuning(ctypes.Structure):
@@ -64,6 +67,13 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"libdsort.so is not built ({path}); run `python -m "
                            f"paper_1002_4464_amd.build` or __graft_entry__.build()")
+    # PyTorch-ROCm ships its own HIP runtime under the same soname as /opt/rocm's.  Load torch
+    # first so that libdsort binds to the runtime that owns torch's device memory and streams;
+    # the other order puts two HIP runtimes in one process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P, U64_, I = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
     lib.dsort_plan.argtypes = [ctypes.POINTER(P), I, I, U64_, U64_, ctypes.POINTER(Tuning),
@@ -85,6 +95,8 @@ def load_library(path: str = LIB_PATH):
                                       ctypes.POINTER(ctypes.c_float),
                                       ctypes.POINTER(ctypes.c_uint32), I, ctypes.POINTER(I)]
     lib.dsort_stage_times.restype = I
+    lib.dsort_last_error.argtypes = []
+    lib.dsort_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 

@@ -48,10 +48,10 @@ struct Geom {
     // workspace byte offsets
     size_t o_status = 0, o_wkeys = 0, o_wvals = 0;
     size_t o_samp = 0, o_samp_sorted = 0, o_samp_tmp = 0;
-    size_t o_counts = 0, o_offs = 0, o_partial = 0;
+    size_t o_counts = 0, o_offs = 0, o_pdst = 0, o_psrc = 0, o_partial = 0;
     size_t o_buckets1 = 0, o_tileoff2 = 0;
-    size_t o_samp2 = 0, o_samp2_sorted = 0, o_counts2 = 0, o_offs2 = 0;
-    size_t o_final = 0;
+    size_t o_samp2 = 0, o_samp2_sorted = 0, o_counts2 = 0, o_offs2 = 0, o_pdst2 = 0, o_psrc2 = 0;
+    size_t o_final = 0, o_lists = 0;
     size_t total = 0;
 };
 
@@ -81,6 +81,9 @@ int timing_summary(Timing &t, const char **names, float *avg_ms, uint32_t *launc
 // Enqueues the whole pipeline (kernels.hip).  Pointers are device pointers; tm may be null.
 int run_pipeline(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, void *stream,
                  Timing *tm);
+
+// Last failure of this thread, for dsort_last_error() (plan.cpp).
+void set_last_error(const char *stage, const char *name, const char *text);
 
 constexpr uint64_t kMaxItems = (1ull << 32) - (1ull << 16);
 

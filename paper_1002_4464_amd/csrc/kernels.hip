@@ -63,6 +63,13 @@ template <class T> __device__ __forceinline__ uint32_t pidx(uint32_t i) {
 }
 template <class T> constexpr uint32_t lds_elems(uint32_t cap) { return cap + (cap >> PadShift<T>::v); }
 
+// pidx of 32-bit item t*E + k for a blocked layout, split into a per-thread base plus a
+// compile-time offset (E a power of two: no pad boundary falls inside [tE, tE + min(E,32))).
+template <int E> __device__ __forceinline__ uint32_t pblk_base(uint32_t t) {
+    return t * E + ((t * E) >> 5);
+}
+template <int E> constexpr uint32_t pblk_off(int k) { return (uint32_t)(k + (k >> 5)); }
+
 // f32 <-> IEEE totalOrder image.
 __device__ __forceinline__ uint32_t f32_in(uint32_t b) {
     return b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u);
@@ -119,7 +126,7 @@ template <> struct KeyMax<uint64_t> { static constexpr uint64_t v = ~0ull; };
 // A set of segments (independent sort problems) and their partition into tiles of L items.
 // seg == nullptr means one segment [0, n_single).
 struct SegView {
-    const uint2 *seg;          // {begin, size} per segment
+    const uint4 *seg;          // {begin, size, ...} per segment
     const uint32_t *tile_off;  // G+1 entries: exclusive prefix of ceil(size/L) over segments
     uint32_t G;
     uint32_t n_single;
@@ -149,7 +156,7 @@ __device__ __forceinline__ bool locate_tile(const SegView &sv, uint32_t L, uint3
     o.tile0 = sv.tile_off[lo];
     o.m = sv.tile_off[lo + 1] - o.tile0;
     o.i = t - o.tile0;
-    const uint2 d = sv.seg[lo];
+    const uint4 d = sv.seg[lo];
     o.seg_begin = d.x;
     o.seg_size = d.y;
     // Defensive: tables written by earlier kernels must describe tiles inside the array.
@@ -185,6 +192,29 @@ template <class T, int E> __device__ __forceinline__ void reg_sort(T (&x)[E]) {
                         cmpx(x[i + j], x[i + j + k]);
 }
 
+// Byte offset of padded LDS element i: (i + (i >> shift)) << log2(sizeof(T)) as one
+// v_add_lshl_u32 (the compiler otherwise splits the scaling into three instructions).
+template <class T> struct SizeLog2;
+template <> struct SizeLog2<uint32_t> { static constexpr int v = 2; };
+template <> struct SizeLog2<uint64_t> { static constexpr int v = 3; };
+template <> struct SizeLog2<C128> { static constexpr int v = 4; };
+
+#define DS_LDS __attribute__((address_space(3)))
+
+template <class T> __device__ __forceinline__ T lds_load(const DS_LDS T *p) { return *p; }
+template <> __device__ __forceinline__ C128 lds_load<C128>(const DS_LDS C128 *p) {
+    return C128{p->key, p->pos, 0u};
+}
+
+template <class T> __device__ __forceinline__ T lds_at(const T *lds, uint32_t i) {
+    uint32_t off;
+    asm("v_add_lshl_u32 %0, %1, %2, %3"
+        : "=v"(off)
+        : "v"(i), "v"(i >> PadShift<T>::v), "i"(SizeLog2<T>::v));
+    const DS_LDS char *base = (const DS_LDS char *)lds;
+    return lds_load<T>((const DS_LDS T *)(base + off));
+}
+
 // Merge path: number of A items among the first `diag` outputs of the stable merge of
 // A = lds[a0, a0+na) and B = lds[b0, b0+nb) (A wins ties).
 template <class T>
@@ -194,11 +224,30 @@ __device__ __forceinline__ uint32_t merge_path(const T *lds, uint32_t a0, uint32
     uint32_t hi = diag < na ? diag : na;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        const T av = lds[pidx<T>(a0 + mid)];
-        const T bv = lds[pidx<T>(b0 + diag - 1 - mid)];
+        const T av = lds_at<T>(lds, a0 + mid);
+        const T bv = lds_at<T>(lds, b0 + diag - 1 - mid);
         if (lt(bv, av)) hi = mid; else lo = mid + 1;
     }
     return lo;
+}
+
+// Serial stable merge of E outputs starting at A index ai (< a_end) / B index bi (< b_end),
+// for an LDS array with one readable element past every index it can reach (so no clamp).
+template <class T, int E>
+__device__ __forceinline__ void serial_merge_nc(const T *lds, uint32_t ai, uint32_t a_end,
+                                                uint32_t bi, uint32_t b_end, T (&out)[E]) {
+    T av = lds_at<T>(lds, ai);
+    T bv = lds_at<T>(lds, bi);
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const bool take_a = (bi >= b_end) || ((ai < a_end) && !lt(bv, av));
+        out[k] = take_a ? av : bv;
+        ai += take_a ? 1u : 0u;
+        bi += take_a ? 0u : 1u;
+        const T v = lds_at<T>(lds, take_a ? ai : bi);
+        av = take_a ? v : av;
+        bv = take_a ? bv : v;
+    }
 }
 
 // Serial stable merge of E outputs starting at A index ai (< a_end) / B index bi (< b_end).
@@ -222,10 +271,11 @@ __device__ __forceinline__ void serial_merge(const T *lds, uint32_t ai, uint32_t
     }
 }
 
-// Sorts lds[0, P) in place (P a power of two, E <= P <= E * blockDim.x).  Thread t owns
+// Sorts lds[0, P) in place (P a power of two, E <= P <= E * blockDim.x; lds must hold
+// lds_elems(P) + 1 elements, the last one only ever read speculatively).  Thread t owns
 // items [tE, tE+E): a register network sorts them, then log2(P/E) merge passes double the
 // sorted run length.  All threads of the block must call it.
-template <class T, int E> __device__ void block_sort(T *lds, uint32_t P) {
+template <class T, int E> __device__ __forceinline__ void block_sort(T *lds, uint32_t P) {
     const uint32_t t = threadIdx.x;
     const bool act = t * E < P;
     T x[E];
@@ -243,8 +293,7 @@ template <class T, int E> __device__ void block_sort(T *lds, uint32_t P) {
             const uint32_t base = start & ~(2 * R - 1);
             const uint32_t diag = start - base;
             const uint32_t a = merge_path<T>(lds, base, R, base + R, R, diag);
-            serial_merge<T, E>(lds, base + a, base + R, base + R + diag - a, base + 2 * R,
-                               base + 2 * R - 1, x);
+            serial_merge_nc<T, E>(lds, base + a, base + R, base + R + diag - a, base + 2 * R, x);
         }
         __syncthreads();
         if (act) {
@@ -253,6 +302,222 @@ template <class T, int E> __device__ void block_sort(T *lds, uint32_t P) {
         }
     }
     __syncthreads();
+}
+
+// ------------------------------------------------------------------------------ block radix sort
+
+// Inclusive prefix sum over the 64 lanes of a wave with DPP moves: shifts by 1, 2, 4, 8 within
+// each row of 16 lanes, then row broadcasts of lane 15 (into rows 1, 3) and lane 31 (rows 2, 3).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false); // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false); // row_bcast:31
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x = min(x, (uint32_t)__shfl_xor(x, d, 64));
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x = max(x, (uint32_t)__shfl_xor(x, d, 64));
+    return x;
+}
+
+// Exclusive scan of one value per thread over the block (blockDim a multiple of 64, at most
+// 1024); *total receives the block sum.  wsum: LDS scratch of 17 words.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *wsum, uint32_t &total) {
+    const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
+    const uint32_t inc = wave_incl_scan(x);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        const uint32_t v = lane < nw ? wsum[lane] : 0u;
+        const uint32_t vi = wave_incl_scan(v);
+        if (lane < nw) wsum[lane] = vi - v;
+        if (lane == nw - 1) wsum[16] = vi;
+    }
+    __syncthreads();
+    total = wsum[16];
+    return wsum[w] + inc - x;
+}
+
+// Block-wide min and max of one value per thread.  red: LDS scratch of 34 words.
+__device__ __forceinline__ void block_minmax(uint32_t lo, uint32_t hi, uint32_t *red,
+                                             uint32_t &mn, uint32_t &mx) {
+    const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if (lane == 0) {
+        red[w] = lo;
+        red[16 + w] = hi;
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t a = red[0], b = red[16];
+        for (uint32_t i = 1; i < nw; ++i) {
+            a = min(a, red[i]);
+            b = max(b, red[16 + i]);
+        }
+        red[32] = a;
+        red[33] = b;
+    }
+    __syncthreads();
+    mn = red[32];
+    mx = red[33];
+}
+
+constexpr uint32_t kRadixBits = 4;
+
+// Stable LSD radix sort (4-bit digits) of the E * blockDim 32-bit keys held in registers, thread
+// t holding positions tE .. tE+E-1, ordered over bits [0, nbits) (the caller subtracts the
+// block's minimum key first).  Each pass: every thread counts its digits in its own column of
+// two 16-bit counters per word (digit d in word d mod 8, half d / 8), a raking scan over
+// (word, thread) turns the counts into the position of every thread's first key of every digit,
+// and keys scatter to those positions in LDS and are read back blocked.  The counters live in
+// the key buffer itself (keys are in registers while counting), so the sort needs only sk
+// (lds_elems(E * blockDim) words; 8 * blockDim <= that) plus 17 words of wsum.  On return
+// sk[pidx(i)] holds the sorted keys (sv the values).  Requires E * blockDim <= 65535.
+template <int E, bool V, uint32_t BD>
+__device__ __forceinline__ void block_radix_sort(uint32_t (&key)[E], uint32_t (&val)[E], uint32_t *sk,
+                                 uint32_t *sv, uint32_t *wsum, uint32_t nbits) {
+    const uint32_t t = threadIdx.x;
+    const uint32_t pb = pblk_base<E>(t);
+    uint32_t *cnt = sk;
+    if (nbits == 0) {  // every key equal: the input order is the stable order
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            sk[pb + pblk_off<E>(k)] = key[k];
+            if (V) sv[pb + pblk_off<E>(k)] = val[k];
+        }
+        __syncthreads();
+        return;
+    }
+    for (uint32_t sh = 0; sh < nbits; sh += kRadixBits) {
+#pragma unroll
+        for (int l = 0; l < 8; ++l) cnt[l * BD + t] = 0;
+        uint32_t r[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            // The counter updates form one sequential chain through LDS anyway; computing each
+            // address just before its update keeps E addresses from being live at once.
+            asm volatile("" : "+v"(key[k])::"memory");
+            const uint32_t a = __builtin_amdgcn_ubfe(key[k], sh, 3) * BD + t;
+            const uint32_t hs = __builtin_amdgcn_ubfe(key[k], sh + 3, 1) << 4;
+            const uint32_t old = cnt[a];
+            cnt[a] = old + (1u << hs);
+            r[k] = __builtin_amdgcn_ubfe(old, hs, 16);
+        }
+        __syncthreads();
+        uint32_t seg[8];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            seg[i] = cnt[8 * t + i];
+            sum += seg[i];
+        }
+        uint32_t total;
+        uint32_t run = block_excl_scan(sum, wsum, total);
+        const uint32_t hi_off = (total & 0xFFFFu) << 16;  // low-half digits precede high-half ones
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            cnt[8 * t + i] = run + hi_off;
+            run += seg[i];
+        }
+        __syncthreads();
+        // Recompute each key's counter address rather than keeping 2E values live across the
+        // scan: the empty asm hides that the keys are unchanged.
+#pragma unroll
+        for (int k = 0; k < E; ++k) asm volatile("" : "+v"(key[k]));
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const uint32_t a = __builtin_amdgcn_ubfe(key[k], sh, 3) * BD + t;
+            const uint32_t hs = __builtin_amdgcn_ubfe(key[k], sh + 3, 1) << 4;
+            r[k] += __builtin_amdgcn_ubfe(cnt[a], hs, 16);
+        }
+        __syncthreads();  // every counter read before the keys overwrite them
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            sk[pidx<uint32_t>(r[k])] = key[k];
+            if (V) sv[pidx<uint32_t>(r[k])] = val[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            key[k] = sk[pb + pblk_off<E>(k)];
+            if (V) val[k] = sv[pb + pblk_off<E>(k)];
+        }
+        __syncthreads();  // every key read before the next pass zeroes counters over them
+    }
+}
+
+// Loads the block's staged keys sk[0, count) (padded index) into registers, blocked, as offsets
+// from the block's smallest real key, with pads (positions >= count) set to the largest real
+// key so they stay behind every real key in a stable sort; returns the key range.
+template <int E>
+__device__ __forceinline__ void load_blocked_with_range(const uint32_t *sk, uint32_t count,
+                                                        uint32_t (&key)[E], uint32_t *red,
+                                                        uint32_t &kmin, uint32_t &kmax) {
+    const uint32_t t = threadIdx.x;
+    const uint32_t pb = pblk_base<E>(t);
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const uint32_t i = t * E + k;
+        key[k] = sk[pb + pblk_off<E>(k)];
+        if (i < count) {
+            lo = min(lo, key[k]);
+            hi = max(hi, key[k]);
+        }
+    }
+    block_minmax(lo, hi, red, kmin, kmax);
+#pragma unroll
+    for (int k = 0; k < E; ++k) key[k] = (t * E + k >= count) ? kmax - kmin : key[k] - kmin;
+}
+
+__device__ __forceinline__ uint32_t range_bits(uint32_t kmin, uint32_t kmax) {
+    return kmax > kmin ? 32u - (uint32_t)__clz(kmax - kmin) : 0u;
+}
+
+// Steps 1-3 for 32-bit keys without values: one workgroup (1024 threads, 16 keys each) per
+// sublist of L <= 16384 items; the local sort is the block radix sort above.
+// Eight waves per SIMD (64 VGPRs) lets two 1024-thread workgroups share a CU; the compiler
+// spills a few dwords for it, which costs less than the lost occupancy.
+template <bool XIN, uint32_t BD>
+__global__ __launch_bounds__(BD) __attribute__((amdgpu_waves_per_eu(8))) void k_tile_radix(const uint32_t *src, uint32_t *dst,
+                                                   SegView sv, uint32_t L, uint32_t s,
+                                                   uint64_t *samples) {
+    constexpr int E = 16;
+    __shared__ uint32_t sk[lds_elems<uint32_t>(E * BD)];
+    __shared__ uint32_t wsum[17], red[34];
+    const uint32_t tid = threadIdx.x, bd = blockDim.x;
+    TileLoc loc;
+    if (!locate_tile(sv, L, blockIdx.x, loc)) return;
+    const uint32_t begin = loc.seg_begin + loc.i * L;
+    const uint32_t count = min(L, loc.seg_size - loc.i * L);
+    for (uint32_t i = tid; i < count; i += bd) {
+        uint32_t k = src[begin + i];
+        if (XIN) k = f32_in(k);
+        sk[pidx<uint32_t>(i)] = k;
+    }
+    __syncthreads();
+    uint32_t key[E], dummy[E];
+    uint32_t kmin, kmax;
+    load_blocked_with_range<E>(sk, count, key, red, kmin, kmax);
+    block_radix_sort<E, false, BD>(key, dummy, sk, nullptr, wsum, range_bits(kmin, kmax));
+    const uint32_t w = L / s;
+    for (uint32_t k = tid; k < s; k += bd) {
+        const uint32_t r = (k + 1) * w - 1;
+        const uint32_t kr = r < count ? sk[pidx<uint32_t>(r)] + kmin : 0xFFFFFFFFu;  // pads
+        samples[(size_t)(loc.tile0 + loc.i) * s + k] = ((uint64_t)kr << 32) | (loc.i * L + r);
+    }
+    for (uint32_t i = tid; i < count; i += bd) dst[begin + i] = sk[pidx<uint32_t>(i)] + kmin;
 }
 
 // ------------------------------------------------------------------------------ Steps 1-3, 9
@@ -278,7 +543,7 @@ template <class K, bool V, int E, int CAP, int MODE, bool XIN, bool XOUT>
 __global__ __launch_bounds__(CAP / E) void k_tile(TileArgs a) {
     using R = Tr<K, V>;
     using T = typename R::T;
-    __shared__ T lds[lds_elems<T>(CAP)];
+    __shared__ T lds[lds_elems<T>(CAP) + 1];
     const uint32_t tid = threadIdx.x;
     const uint32_t bd = blockDim.x;
 
@@ -290,7 +555,7 @@ __global__ __launch_bounds__(CAP / E) void k_tile(TileArgs a) {
         count = min(a.L, loc.seg_size - loc.i * a.L);
         P = a.L;
     } else {
-        uint2 d = a.sv.seg ? a.sv.seg[blockIdx.x] : make_uint2(0u, a.sv.n_single);
+        uint4 d = a.sv.seg ? a.sv.seg[blockIdx.x] : make_uint4(0u, a.sv.n_single, 0u, 0u);
         begin = d.x;
         count = d.y;
         if (count == 0) return;
@@ -360,7 +625,7 @@ __global__ __launch_bounds__(CAP / E) void k_sort_samples(const SC *src, SC *dst
                                                           uint32_t L, uint32_t s,
                                                           uint32_t chunk_total,
                                                           uint32_t *status) {
-    __shared__ SC lds[lds_elems<SC>(CAP)];
+    __shared__ SC lds[lds_elems<SC>(CAP) + 1];
     const uint32_t tid = threadIdx.x;
     uint32_t begin, count;
     if (chunk_total) {  // fixed chunks of CAP
@@ -437,7 +702,8 @@ __global__ __launch_bounds__(CAP / E) void k_merge_round(const SC *src, SC *dst,
 
 // One workgroup per sublist; lane j locates global sample g_j = S[(j+1) m - 1] of the
 // sublist's segment: r_ij = #{x : (A_i[x], i*L + x) <= g_j}, a monotone predicate on the
-// sorted sublist, found by bisection.  Pads (x >= count) are key-max items.
+// sorted sublist, found by bisection in global memory (the first probes, shared by all lanes,
+// hit the caches).  Pads (x >= count) are key-max items.
 template <class K, bool V>
 __global__ __launch_bounds__(256) void k_rank(const K *keys, const void *sorted_samples,
                                               uint32_t *counts, SegView sv, uint32_t L,
@@ -469,83 +735,178 @@ __global__ __launch_bounds__(256) void k_rank(const K *keys, const void *sorted_
 
 // ------------------------------------------------------------------------------ Step 7
 
-// Exclusive scan of v[0, n) in LDS by thread 0 (n <= 1024); returns the total.
-__device__ __forceinline__ uint32_t lds_scan_serial(uint32_t *v, uint32_t n) {
+// Exclusive scan of v[0, n) in LDS (any n) by the first wave; returns the total.  Every
+// thread of the block must call it.
+__device__ uint32_t lds_scan(uint32_t *v, uint32_t n) {
     __shared__ uint32_t total;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (uint32_t j = 0; j < n; ++j) {
-            const uint32_t x = v[j];
-            v[j] = run;
-            run += x;
+    if (threadIdx.x < 64) {
+        const uint32_t lane = threadIdx.x;
+        uint32_t carry = 0;
+        for (uint32_t b = 0; b < n; b += 64) {
+            const uint32_t j = b + lane;
+            const uint32_t x = j < n ? v[j] : 0u;
+            uint32_t inc = x;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t y = __shfl_up(inc, d, 64);
+                if (lane >= (uint32_t)d) inc += y;
+            }
+            if (j < n) v[j] = carry + inc - x;
+            carry += __shfl(inc, 63, 64);
         }
-        total = run;
+        if (lane == 0) total = carry;
     }
     __syncthreads();
     return total;
 }
 
-// Writes the bucket table {begin, real size} of one segment and, when asked, the tile map of
-// the next level (ceil(size / L_next) per bucket, exclusive prefix, G_next + 1 entries).
-// Pads are the largest items, so after Step 8 they fill exactly [seg_size, n') of the
-// segment; a bucket's real size is its overlap with [0, seg_size) (several trailing buckets
-// may hold pads when the last sublist is mostly padding).
+// Size classes of the final buckets: the scan kernels append every non-empty bucket to the
+// work list of the smallest class that holds it, and one kernel per class (sized for that
+// capacity) sorts the buckets on its list.
+constexpr int kMaxClasses = 8;
+struct Classes {
+    uint32_t n;                  // 0: buckets feed another level instead
+    uint32_t cap[kMaxClasses];   // ascending capacities (items)
+    uint32_t *count;             // n counters, zeroed by k_init
+    uint32_t *list;              // n lists of `stride` bucket indices
+    uint32_t stride;
+};
+
+// Bucket table of one segment: {begin, real size, first piece, pieces}.  Pieces of bucket j are
+// the m pieces A_1j..A_mj, stored bucket-major from `piece0 + j*m`.  Pads are the largest items,
+// so after Step 8 they fill exactly [seg_size, n') of the segment; a bucket's real size is its
+// overlap with [0, seg_size) (several trailing buckets may hold pads when the last sublist is
+// mostly padding).  When asked, also the tile map of the next level: ceil(size / L_next)
+// tiles per bucket, exclusive prefix, s + 1 entries.  `bucket0` is the global index of the
+// segment's first bucket (for the class work lists).
 __device__ void emit_buckets(const uint32_t *colsum, const uint32_t *colbase, uint32_t s,
-                             uint32_t seg_begin, uint32_t seg_size, uint2 *buckets,
-                             uint32_t *tile_off_next, uint32_t L_next, uint32_t *tmp) {
-    for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) {
+                             uint32_t seg_begin, uint32_t seg_size, uint32_t piece0, uint32_t m,
+                             uint4 *buckets, uint32_t *tile_off_next, uint32_t L_next,
+                             uint32_t *tmp, const Classes &cls, uint32_t bucket0) {
+    __shared__ uint32_t ccount[kMaxClasses], cbase[kMaxClasses];
+    if (threadIdx.x < (uint32_t)kMaxClasses) ccount[threadIdx.x] = 0;
+    __syncthreads();
+    // class of each bucket and its slot among this workgroup's buckets of that class
+    uint32_t mycls[4], myslot[4];
+    for (uint32_t r = 0; r < 4; ++r) {
+        const uint32_t j = threadIdx.x + r * blockDim.x;
+        mycls[r] = kMaxClasses;
+        if (j >= s) continue;
         const uint32_t b = colbase[j];
         const uint32_t size = b >= seg_size ? 0u : min(colsum[j], seg_size - b);
-        buckets[j] = make_uint2(seg_begin + colbase[j], size);
+        buckets[j] = make_uint4(seg_begin + b, size, piece0 + j * m, m);
         if (tile_off_next) tmp[j] = (size + L_next - 1) / L_next;
+        if (cls.n && size) {
+            uint32_t c = 0;
+            while (c + 1 < cls.n && cls.cap[c] < size) ++c;
+            mycls[r] = c;
+            myslot[r] = atomicAdd(&ccount[c], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < cls.n && ccount[threadIdx.x])
+        cbase[threadIdx.x] = atomicAdd(&cls.count[threadIdx.x], ccount[threadIdx.x]);
+    __syncthreads();
+    for (uint32_t r = 0; r < 4; ++r) {
+        const uint32_t j = threadIdx.x + r * blockDim.x;
+        if (mycls[r] == (uint32_t)kMaxClasses) continue;
+        const uint32_t at = cbase[mycls[r]] + myslot[r];
+        if (at < cls.stride) cls.list[(size_t)mycls[r] * cls.stride + at] = bucket0 + j;
     }
     if (tile_off_next) {
-        const uint32_t tot = lds_scan_serial(tmp, s);
+        const uint32_t tot = lds_scan(tmp, s);
         for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) tile_off_next[j] = tmp[j];
         if (threadIdx.x == 0) tile_off_next[s] = tot;
     }
 }
 
-// One workgroup per segment (segments with at most a few thousand sublists).
-__global__ __launch_bounds__(256) void k_scan_small(const uint32_t *counts, uint32_t *offs,
-                                                    SegView sv, uint32_t L, uint32_t s,
-                                                    uint2 *buckets, uint32_t *tile_off_next,
-                                                    uint32_t L_next) {
-    __shared__ uint32_t colsum[1024], colbase[1024], tmp[1024];
-    uint32_t tile0, m, seg_begin, seg_size;
-    if (!sv.tile_off) {
-        tile0 = 0; m = (sv.n_single + L - 1) / L; seg_begin = 0; seg_size = sv.n_single;
-    } else {
-        tile0 = sv.tile_off[blockIdx.x];
-        if (sv.tile_off[blockIdx.x + 1] > sv.max_tiles) return;
-        m = sv.tile_off[blockIdx.x + 1] - tile0;
-        seg_begin = sv.seg[blockIdx.x].x;
-        seg_size = sv.seg[blockIdx.x].y;
+constexpr uint32_t kScanLds = 8192;  // entries of one row-block buffer
+
+// For rows [r0, r1) of one segment (first row tile0, m rows, s columns) writes l_ij both
+// row-major (`offs`) and bucket-major (`pdst`, entry tile0*s + j*m + i), and the source
+// position of piece A_ij, seg_begin + i*L + sum_{j'<j} a_ij' (`psrc`, bucket-major).
+// colstart[j] (LDS) holds l_{r0,j} on entry and is advanced.  C, Lm: LDS, kScanLds entries.
+__device__ void scan_rows(const uint32_t *counts, uint32_t *offs, uint32_t *pdst, uint32_t *psrc,
+                          uint32_t tile0, uint32_t m, uint32_t r0, uint32_t r1, uint32_t s,
+                          uint32_t seg_begin, uint32_t L, uint32_t *colstart, uint32_t *C,
+                          uint32_t *Lm) {
+    const uint32_t tid = threadIdx.x, bd = blockDim.x;
+    const uint32_t SB = kScanLds / s;
+    const size_t pbase = (size_t)tile0 * s;
+    for (uint32_t rb = r0; rb < r1; rb += SB) {
+        const uint32_t nrow = min(SB, r1 - rb);
+        const size_t rowq = (size_t)(tile0 + rb) * s;
+        for (uint32_t q = tid; q < nrow * s; q += bd) C[q] = counts[rowq + q];
+        __syncthreads();
+        for (uint32_t j = tid; j < s; j += bd) {  // column prefix: l_ij
+            uint32_t run = colstart[j];
+            for (uint32_t r = 0; r < nrow; ++r) {
+                Lm[r * s + j] = run;
+                run += C[r * s + j];
+            }
+            colstart[j] = run;
+        }
+        __syncthreads();
+        {  // row prefix in place: C becomes the start rank of each piece in its sublist
+            const uint32_t lane = tid & 63, w = tid >> 6, nw = bd >> 6;
+            for (uint32_t r = w; r < nrow; r += nw) {
+                uint32_t carry = 0;
+                for (uint32_t b = 0; b < s; b += 64) {
+                    const uint32_t j = b + lane;
+                    const uint32_t x = j < s ? C[r * s + j] : 0u;
+                    uint32_t inc = x;
+#pragma unroll
+                    for (int d = 1; d < 64; d <<= 1) {
+                        const uint32_t y = __shfl_up(inc, d, 64);
+                        if (lane >= (uint32_t)d) inc += y;
+                    }
+                    if (j < s) C[r * s + j] = carry + inc - x;
+                    carry += __shfl(inc, 63, 64);
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t q = tid; q < nrow * s; q += bd) offs[rowq + q] = Lm[q];
+        for (uint32_t q = tid; q < nrow * s; q += bd) {
+            const uint32_t r = q % nrow, j = q / nrow;
+            const size_t e = pbase + (size_t)j * m + rb + r;
+            pdst[e] = Lm[r * s + j];
+            psrc[e] = seg_begin + (rb + r) * L + C[r * s + j];
+        }
+        __syncthreads();
     }
-    const uint32_t *C = counts + (size_t)tile0 * s;
-    uint32_t *O = offs + (size_t)tile0 * s;
+}
+
+// Step 7 for many segments, one workgroup each (second level): column sums, their exclusive
+// scan (bucket starts), the bucket table, then every l_ij and piece source.
+__global__ __launch_bounds__(256) void k_scan_seg(const uint32_t *counts, uint32_t *offs,
+                                                  uint32_t *pdst, uint32_t *psrc, SegView sv,
+                                                  uint32_t L, uint32_t s, uint4 *buckets,
+                                                  Classes cls) {
+    __shared__ uint32_t colsum[1024], colbase[1024], C[kScanLds], Lm[kScanLds];
+    const uint32_t g = blockIdx.x;
+    if (sv.tile_off[g + 1] > sv.max_tiles) return;
+    const uint32_t tile0 = sv.tile_off[g];
+    const uint32_t m = sv.tile_off[g + 1] - tile0;
+    const uint32_t seg_begin = sv.seg[g].x, seg_size = sv.seg[g].y;
     for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) {
         uint32_t sum = 0;
-        for (uint32_t i = 0; i < m; ++i) sum += C[(size_t)i * s + j];
+        for (uint32_t i = 0; i < m; ++i) sum += counts[(size_t)(tile0 + i) * s + j];
         colsum[j] = sum;
         colbase[j] = sum;
     }
-    lds_scan_serial(colbase, s);
-    for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) {
-        uint32_t run = seg_begin + colbase[j];
-        for (uint32_t i = 0; i < m; ++i) {
-            O[(size_t)i * s + j] = run;
-            run += C[(size_t)i * s + j];
-        }
-    }
-    emit_buckets(colsum, colbase, s, seg_begin, seg_size, buckets + (size_t)blockIdx.x * s,
-                 tile_off_next, L_next, tmp);
+    lds_scan(colbase, s);
+    emit_buckets(colsum, colbase, s, seg_begin, seg_size, tile0 * s, m, buckets + (size_t)g * s,
+                 nullptr, 0u, nullptr, cls, g * s);
+    for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) colsum[j] = seg_begin + colbase[j];
+    __syncthreads();
+    scan_rows(counts, offs, pdst, psrc, tile0, m, 0, m, s, seg_begin, L, colsum, C, Lm);
 }
 
-// Three-kernel form for one large segment [0, n): (a) column sums of each block of RB rows,
-// (b) one workgroup scans them per column and across columns, (c) every block writes its
-// offsets.
+// Step 7 for one segment [0, n) with many sublists, in three kernels: (a) column sums of each
+// block of RB rows, (b) one workgroup scans them per column and across columns, (c) every row
+// block writes its l_ij and piece sources.
 __global__ __launch_bounds__(256) void k_scan_partial(const uint32_t *counts, uint32_t *partial,
                                                       uint32_t m, uint32_t s, uint32_t RB) {
     const uint32_t i0 = blockIdx.x * RB, i1 = min(m, i0 + RB);
@@ -556,9 +917,10 @@ __global__ __launch_bounds__(256) void k_scan_partial(const uint32_t *counts, ui
     }
 }
 
-__global__ __launch_bounds__(256) void k_scan_mid(uint32_t *partial, uint32_t nrb, uint32_t s,
-                                                  uint32_t n, uint2 *buckets,
-                                                  uint32_t *tile_off_next, uint32_t L_next) {
+__global__ __launch_bounds__(256) void k_scan_mid(uint32_t *partial, uint32_t nrb, uint32_t m,
+                                                  uint32_t s, uint32_t n, uint4 *buckets,
+                                                  uint32_t *tile_off_next, uint32_t L_next,
+                                                  Classes cls) {
     __shared__ uint32_t colsum[1024], colbase[1024], tmp[1024];
     for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) {
         uint32_t run = 0;
@@ -570,29 +932,30 @@ __global__ __launch_bounds__(256) void k_scan_mid(uint32_t *partial, uint32_t nr
         colsum[j] = run;
         colbase[j] = run;
     }
-    lds_scan_serial(colbase, s);
+    lds_scan(colbase, s);
     for (uint32_t j = threadIdx.x; j < s; j += blockDim.x)
         for (uint32_t b = 0; b < nrb; ++b) partial[(size_t)b * s + j] += colbase[j];
-    emit_buckets(colsum, colbase, s, 0u, n, buckets, tile_off_next, L_next, tmp);
+    emit_buckets(colsum, colbase, s, 0u, n, 0u, m, buckets, tile_off_next, L_next, tmp, cls, 0u);
 }
 
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *counts, const uint32_t *partial,
-                                                    uint32_t *offs, uint32_t m, uint32_t s,
-                                                    uint32_t RB) {
+                                                    uint32_t *offs, uint32_t *pdst, uint32_t *psrc,
+                                                    uint32_t m, uint32_t s, uint32_t RB,
+                                                    uint32_t L) {
+    __shared__ uint32_t colstart[1024], C[kScanLds], Lm[kScanLds];
     const uint32_t i0 = blockIdx.x * RB, i1 = min(m, i0 + RB);
-    for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) {
-        uint32_t run = partial[(size_t)blockIdx.x * s + j];
-        for (uint32_t i = i0; i < i1; ++i) {
-            offs[(size_t)i * s + j] = run;
-            run += counts[(size_t)i * s + j];
-        }
-    }
+    for (uint32_t j = threadIdx.x; j < s; j += blockDim.x)
+        colstart[j] = partial[(size_t)blockIdx.x * s + j];
+    __syncthreads();
+    scan_rows(counts, offs, pdst, psrc, 0u, m, i0, i1, s, 0u, L, colstart, C, Lm);
 }
 
 // ------------------------------------------------------------------------------ Step 8
 
 // One workgroup per sorted sublist: item r of piece j (ranks [st_j, st_{j+1})) moves to
-// l_ij + r - st_j.  Pads (r >= count) are never written.
+// l_ij + r - st_j.  Each wave streams a contiguous slice of the sublist 64 items at a time (loads
+// coalesced; stores contiguous within a piece), every lane following the piece its item is in.
+// Pads (r >= count) are never written.  Used between the two levels.
 template <class K, bool V>
 __global__ __launch_bounds__(256) void k_relocate(const K *src, K *dst, const uint32_t *src_vals,
                                                   uint32_t *dst_vals, const uint32_t *counts,
@@ -601,31 +964,318 @@ __global__ __launch_bounds__(256) void k_relocate(const K *src, K *dst, const ui
     __shared__ uint32_t st[1025], of[1024];
     TileLoc loc;
     if (!locate_tile(sv, L, blockIdx.x, loc)) return;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
     const uint32_t base = loc.seg_begin + loc.i * L;
     const uint32_t count = min(L, loc.seg_size - loc.i * L);
     const size_t row = (size_t)(loc.tile0 + loc.i) * s;
-    for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) {
+    for (uint32_t j = tid; j < s; j += blockDim.x) {
         st[j] = counts[row + j];
         of[j] = offs[row + j];
     }
-    lds_scan_serial(st, s);
-    for (uint32_t r = threadIdx.x; r < count; r += blockDim.x) {
-        uint32_t lo = 0, hi = s - 1;  // largest j with st[j] <= r
+    const uint32_t tot = lds_scan(st, s);
+    if (tid == 0) st[s] = tot;
+    __syncthreads();
+    const uint32_t span = ((count + nw - 1) / nw + 63) & ~63u;
+    const uint32_t r0 = w * span, r1 = min(count, r0 + span);
+    if (r0 >= r1) return;
+    uint32_t p;
+    {
+        uint32_t lo = 0, hi = s - 1;  // largest p with st[p] <= r
+        const uint32_t r = min(r0 + lane, r1 - 1);
         while (lo < hi) {
             const uint32_t mid = (lo + hi + 1) >> 1;
             if (st[mid] <= r) lo = mid; else hi = mid - 1;
         }
-        const uint32_t d = of[lo] + (r - st[lo]);
-        if (d >= sv.n_total) continue;  // defensive: offsets always lie inside the array
-        dst[d] = src[base + r];
-        if (V) dst_vals[d] = src_vals[base + r];
+        p = lo;
+    }
+    for (uint32_t rw = r0; rw < r1; rw += 4 * 64) {
+        K v[4];
+        uint32_t vv[4], d[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t r = rw + 64 * u + lane;
+            if (r < r1) {
+                while (r >= st[p + 1]) ++p;
+                d[u] = of[p] + (r - st[p]);
+                v[u] = src[base + r];
+                if (V) vv[u] = src_vals[base + r];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t r = rw + 64 * u + lane;
+            if (r < r1 && d[u] < sv.n_total) {  // defensive: offsets always lie inside the array
+                dst[d[u]] = v[u];
+                if (V) dst_vals[d[u]] = vv[u];
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------ Steps 8+9
+
+// Merges nr sorted runs lds[bnd[r], bnd[r+1]) (bnd: LDS, bnd[0] = 0, bnd[nr] = total,
+// non-decreasing; empty runs allowed) pairwise, level by level, into one sorted run; earlier
+// runs win ties, so the merge is stable.  At each level every pair of runs is cut into chunks of
+// E outputs (the last one partial), so no chunk straddles two pairs; chunk q goes to slot
+// q = c * blockDim + thread (c < CH).  Requires total / E + ceil(nr / 2) <= CH * blockDim.
+// cp: LDS scratch of at least ceil(nr / 2) + 1 entries.
+template <class T, int E, int CH>
+__device__ __forceinline__ void block_merge_runs(T *lds, const uint32_t *bnd, uint32_t *cp, uint32_t nr,
+                                 uint32_t total) {
+    const uint32_t t = threadIdx.x, bd = blockDim.x;
+    const uint32_t lim = total - 1;
+    T x[CH][E];
+    uint32_t xo[CH], xc[CH];
+    for (uint32_t S = 1; S < nr; S <<= 1) {
+        const uint32_t S2 = 2 * S;
+        const uint32_t npairs = (nr + S2 - 1) / S2;
+        for (uint32_t p = t; p < npairs; p += bd) {
+            const uint32_t st = bnd[min(p * S2, nr)], en = bnd[min(p * S2 + S2, nr)];
+            cp[p] = (en - st + E - 1) / E;
+        }
+        const uint32_t nchunks = lds_scan(cp, npairs);
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const uint32_t q = c * bd + t;
+            xc[c] = 0;
+            if (q < nchunks) {
+                uint32_t lo = 0, hi = npairs - 1;  // pair of chunk q: largest p with cp[p] <= q
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1) >> 1;
+                    if (cp[mid] <= q) lo = mid; else hi = mid - 1;
+                }
+                const uint32_t p = lo;
+                const uint32_t a0 = bnd[min(p * S2, nr)];
+                const uint32_t a1 = bnd[min(p * S2 + S, nr)];
+                const uint32_t b1 = bnd[min(p * S2 + S2, nr)];
+                const uint32_t diag = (q - cp[p]) * E;
+                const uint32_t k = merge_path<T>(lds, a0, a1 - a0, a1, b1 - a1, diag);
+                serial_merge<T, E>(lds, a0 + k, a1, a1 + diag - k, b1, lim, x[c]);
+                xo[c] = a0 + diag;
+                xc[c] = min((uint32_t)E, b1 - xo[c]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                if ((uint32_t)e < xc[c]) lds[pidx<T>(xo[c] + e)] = x[c][e];
+        }
+        __syncthreads();
+    }
+}
+
+struct GatherArgs {
+    const void *src_keys;    // sorted sublists of the last level
+    void *dst_keys;          // output (must not alias src)
+    const uint32_t *src_vals;
+    uint32_t *dst_vals;
+    const uint4 *buckets;    // {begin, size, first piece, pieces}
+    const uint32_t *pdst;    // bucket-major l_ij
+    const uint32_t *psrc;    // bucket-major source position of A_ij
+    const uint32_t *count;   // per class: buckets on its list
+    const uint32_t *list;    // per class: bucket indices
+    uint32_t stride;
+    uint32_t n_total;
+    uint32_t *status;
+};
+
+constexpr uint32_t kMaxPieces = 256;
+constexpr int kGatherE = 16;
+
+// Threads and chunks per thread of the class holding CAP items: enough chunk slots for
+// CAP / E chunks plus one partial chunk per pair of pieces (at most kMaxPieces / 2).
+template <int CAP> struct GatherShape {
+    static constexpr uint32_t need = CAP / kGatherE + kMaxPieces / 2;
+    static constexpr int CH = need <= 1024 ? 1 : (need <= 2048 ? 2 : 3);
+    static constexpr uint32_t BD = ((need + CH - 1) / CH + 63) / 64 * 64;
+    static_assert(BD <= 1024, "class too large for one workgroup");
+};
+
+// Steps 8 and 9 fused, one workgroup per bucket B_j of one size class (persistent: each
+// workgroup walks the class's work list).  Every piece A_ij is read from its sorted sublist
+// straight into LDS at its place l_ij in the bucket (the relocation of Step 8, staged in LDS),
+// then the m sorted pieces are merged into the sorted bucket (Step 9) and written out.
+template <class K, bool V, int CAP, bool XOUT>
+__global__ __launch_bounds__(GatherShape<CAP>::BD) void k_gather_merge(GatherArgs a,
+                                                                     uint32_t cls) {
+    using R = Tr<K, V>;
+    using T = typename R::T;
+    constexpr int E = kGatherE;
+    constexpr uint32_t BD = GatherShape<CAP>::BD;
+    constexpr int CH = GatherShape<CAP>::CH;
+    __shared__ T lds[lds_elems<T>(CAP)];
+    __shared__ uint32_t bnd[kMaxPieces + 1], ps[kMaxPieces], cp[kMaxPieces / 2 + 1];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63, w = tid >> 6, nw = BD >> 6;
+    const uint32_t nwork = min(a.count[cls], a.stride);
+    const uint32_t *list = a.list + (size_t)cls * a.stride;
+    const K *src = (const K *)a.src_keys;
+    K *dst = (K *)a.dst_keys;
+    for (uint32_t item = blockIdx.x; item < nwork; item += gridDim.x) {
+        const uint4 b = a.buckets[list[item]];
+        const uint32_t begin = b.x, total = b.y, pbase = b.z, np = b.w;
+        if (total == 0 || total > CAP || np > kMaxPieces || np == 0 ||
+            (uint64_t)begin + total > a.n_total) {
+            if (tid == 0) atomicOr(a.status, 8u);
+            continue;
+        }
+        __syncthreads();  // the previous bucket is done with the LDS tables
+        for (uint32_t i = tid; i < np; i += BD) {
+            bnd[i] = min(a.pdst[pbase + i] - begin, total);
+            ps[i] = a.psrc[pbase + i];
+        }
+        if (tid == 0) bnd[np] = total;
+        __syncthreads();
+        // Gather: wave w streams its slice of the bucket 64 consecutive items at a time, each
+        // lane following the piece its item falls in.
+        const uint32_t span = ((total + nw - 1) / nw + 63) & ~63u;
+        const uint32_t x_begin = w * span, x_end = min(total, x_begin + span);
+        if (x_begin < x_end) {
+            uint32_t p = 0;
+            {
+                uint32_t lo = 0, hi = np - 1;  // largest p with bnd[p] <= x
+                const uint32_t xs = min(x_begin + lane, total - 1);
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1) >> 1;
+                    if (bnd[mid] <= xs) lo = mid; else hi = mid - 1;
+                }
+                p = lo;
+            }
+            for (uint32_t row = x_begin; row < x_end; row += 4 * 64) {
+                K v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t xu = row + 64 * u + lane;
+                    if (xu < x_end) {
+                        while (xu >= bnd[p + 1]) ++p;
+                        v[u] = src[ps[p] + (xu - bnd[p])];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t xu = row + 64 * u + lane;
+                    if (xu < x_end) lds[pidx<T>(xu)] = R::make(v[u], xu);
+                }
+            }
+        }
+        __syncthreads();
+        block_merge_runs<T, E, CH>(lds, bnd, cp, np, total);
+
+        uint32_t pos[CH][E];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const uint32_t x0 = (c * BD + tid) * E;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const uint32_t x = x0 + e;
+                if (x < total) {
+                    const T el = lds[pidx<T>(x)];
+                    K kk = R::key(el);
+                    if (XOUT) kk = (K)f32_out((uint32_t)kk);
+                    dst[begin + x] = kk;
+                    pos[c][e] = R::lpos(el);
+                }
+            }
+        }
+        if (V) {
+            __syncthreads();
+            uint32_t *lv = (uint32_t *)lds;
+            for (uint32_t i = w; i < np; i += nw) {
+                const uint32_t d0 = bnd[i], len = bnd[i + 1] - d0, s0 = ps[i];
+                for (uint32_t q = lane; q < len; q += 64) lv[d0 + q] = a.src_vals[s0 + q];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const uint32_t x0 = (c * BD + tid) * E;
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    if (x0 + e < total) a.dst_vals[begin + x0 + e] = lv[pos[c][e]];
+            }
+        }
+    }
+}
+
+// Steps 8 and 9 fused for 32-bit keys without values, buckets of at most CAP = 16 * BD
+// items: the pieces are gathered into LDS as above, then the bucket is sorted with the block
+// radix sort over the key range it actually holds.
+template <int CAP, bool XOUT>
+__global__ __launch_bounds__(CAP / 16) __attribute__((amdgpu_waves_per_eu(8))) void k_gather_radix(GatherArgs a, uint32_t cls) {
+    constexpr int E = 16;
+    constexpr uint32_t BD = CAP / E;
+    __shared__ uint32_t sk[lds_elems<uint32_t>(CAP)];
+    __shared__ uint32_t bnd[kMaxPieces + 1], ps[kMaxPieces], wsum[17], red[34];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63, w = tid >> 6, nw = BD >> 6;
+    const uint32_t nwork = min(a.count[cls], a.stride);
+    const uint32_t *list = a.list + (size_t)cls * a.stride;
+    const uint32_t *src = (const uint32_t *)a.src_keys;
+    uint32_t *dst = (uint32_t *)a.dst_keys;
+    for (uint32_t item = blockIdx.x; item < nwork; item += gridDim.x) {
+        const uint4 b = a.buckets[list[item]];
+        const uint32_t begin = b.x, total = b.y, pbase = b.z, np = b.w;
+        if (total == 0 || total > CAP || np > kMaxPieces || np == 0 ||
+            (uint64_t)begin + total > a.n_total) {
+            if (tid == 0) atomicOr(a.status, 8u);
+            continue;
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < np; i += BD) {
+            bnd[i] = min(a.pdst[pbase + i] - begin, total);
+            ps[i] = a.psrc[pbase + i];
+        }
+        if (tid == 0) bnd[np] = total;
+        __syncthreads();
+        const uint32_t span = ((total + nw - 1) / nw + 63) & ~63u;
+        const uint32_t x_begin = w * span, x_end = min(total, x_begin + span);
+        if (x_begin < x_end) {
+            uint32_t p = 0;
+            {
+                uint32_t lo = 0, hi = np - 1;
+                const uint32_t xs = min(x_begin + lane, total - 1);
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1) >> 1;
+                    if (bnd[mid] <= xs) lo = mid; else hi = mid - 1;
+                }
+                p = lo;
+            }
+            for (uint32_t row = x_begin; row < x_end; row += 4 * 64) {
+                uint32_t v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t xu = row + 64 * u + lane;
+                    if (xu < x_end) {
+                        while (xu >= bnd[p + 1]) ++p;
+                        v[u] = src[ps[p] + (xu - bnd[p])];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t xu = row + 64 * u + lane;
+                    if (xu < x_end) sk[pidx<uint32_t>(xu)] = v[u];
+                }
+            }
+        }
+        __syncthreads();
+        uint32_t key[E], dummy[E];
+        uint32_t kmin, kmax;
+        load_blocked_with_range<E>(sk, total, key, red, kmin, kmax);
+        block_radix_sort<E, false, BD>(key, dummy, sk, nullptr, wsum, range_bits(kmin, kmax));
+        for (uint32_t i = tid; i < total; i += BD) {
+            uint32_t kk = sk[pidx<uint32_t>(i)] + kmin;
+            if (XOUT) kk = f32_out(kk);
+            dst[begin + i] = kk;
+        }
     }
 }
 
 // ------------------------------------------------------------------------------ misc
 
 __global__ void k_init(uint32_t *status) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *status = 0;
+    if (threadIdx.x <= (uint32_t)kMaxClasses && blockIdx.x == 0) status[threadIdx.x] = 0;
 }
 
 // ------------------------------------------------------------------------------ host driver
@@ -635,15 +1285,26 @@ __global__ void k_init(uint32_t *status) {
         if (hipGetLastError() != hipSuccess) return DSORT_E_HIP; \
     } while (0)
 
-// Launch with optional timing events around it.
+// Launch with optional timing events around it; a failed launch is recorded for
+// dsort_last_error() with the stage name and the HIP error.
 #define DS_LAUNCH(NAME, KERNEL, GRID, BLOCK, ...)                                   \
     do {                                                                            \
         void *ev1_ = nullptr;                                                       \
-        if (tm && stage_begin(*tm, NAME, st, &ev1_) != DSORT_OK) return DSORT_E_HIP; \
+        if (tm && stage_begin(*tm, NAME, st, &ev1_) != DSORT_OK)                    \
+            return record_error(NAME, hipGetLastError());                           \
         hipLaunchKernelGGL(KERNEL, GRID, BLOCK, 0, st, __VA_ARGS__);                \
-        if (hipGetLastError() != hipSuccess) return DSORT_E_HIP;                    \
-        if (ev1_ && hipEventRecord((hipEvent_t)ev1_, st) != hipSuccess) return DSORT_E_HIP; \
+        {                                                                           \
+            const hipError_t e_ = hipGetLastError();                                \
+            if (e_ != hipSuccess) return record_error(NAME, e_);                    \
+        }                                                                           \
+        if (ev1_ && hipEventRecord((hipEvent_t)ev1_, st) != hipSuccess)             \
+            return record_error(NAME, hipGetLastError());                           \
     } while (0)
+
+int record_error(const char *stage, hipError_t e) {
+    set_last_error(stage, hipGetErrorName(e), hipGetErrorString(e));
+    return DSORT_E_HIP;
+}
 
 void *pool_event(Timing &t) {
     if (t.used == t.pool.size()) {
@@ -664,6 +1325,24 @@ int stage_begin(Timing &t, const char *name, hipStream_t st, void **ev1) {
     return DSORT_OK;
 }
 
+// Size classes of the fused Steps 8-9 per LDS element type (ascending; the last is the bucket
+// capacity of the plan).
+template <class T> struct ClassCaps;
+template <> struct ClassCaps<uint32_t> {
+    static constexpr uint32_t n = 8;
+    static constexpr uint32_t cap[8] = {2048, 4096, 6144, 8192, 10240, 12288, 16384, 32768};
+};
+template <> struct ClassCaps<uint64_t> {
+    static constexpr uint32_t n = 7;
+    static constexpr uint32_t cap[8] = {2048, 4096, 6144, 8192, 10240, 12288, 16384, 0};
+};
+template <> struct ClassCaps<C128> {
+    static constexpr uint32_t n = 5;
+    static constexpr uint32_t cap[8] = {1024, 2048, 4096, 6144, 8192, 0, 0, 0};
+};
+
+constexpr uint32_t kNumCUs = 256;
+
 template <class K, bool V, bool F32> struct Pipeline {
     using R = Tr<K, V>;
     using SC = typename R::SC;
@@ -673,6 +1352,51 @@ template <class K, bool V, bool F32> struct Pipeline {
     static constexpr int FCAP = FE * 1024;                            // bucket capacity
     static constexpr int SE = sizeof(SC) >= 16 ? 8 : 16;
     static constexpr int SCAP = SE * 1024;
+    using T = typename R::T;
+    using CC = ClassCaps<T>;
+    // 32-bit keys without values use the radix local sorts; other layouts the merge sorts.
+    static constexpr bool kRadix = !V && sizeof(K) == 4;
+    static constexpr bool kRadixLevel1 = false;
+    static_assert(CC::cap[CC::n - 1] == (uint32_t)FCAP, "last class must be the bucket capacity");
+
+    static Classes classes(uint32_t *status, uint32_t *lists, uint32_t stride) {
+        Classes c{};
+        c.n = CC::n;
+        for (uint32_t i = 0; i < CC::n; ++i) c.cap[i] = CC::cap[i];
+        c.count = status + 1;
+        c.list = lists;
+        c.stride = stride;
+        return c;
+    }
+
+    // One persistent launch per size class, each sized to fill the chip at its occupancy.
+    template <uint32_t I>
+    static int gather_classes(const GatherArgs &a, hipStream_t st, Timing *tm) {
+        if constexpr (I < CC::n) {
+            constexpr int CAP = (int)CC::cap[I];
+            constexpr uint32_t BD = GatherShape<CAP>::BD;
+            constexpr uint32_t lds = lds_elems<T>(CAP) * sizeof(T) + 8 * (kMaxPieces + 1);
+            constexpr uint32_t by_lds = 163840u / lds;
+            constexpr uint32_t by_waves = 32u / (BD / 64);
+            constexpr uint32_t occ = by_lds < by_waves ? by_lds : by_waves;
+            if constexpr (kRadix && CAP <= 16384) {
+                constexpr uint32_t RBD = CAP / 16;
+                constexpr uint32_t rlds = lds_elems<uint32_t>(CAP) * 4 + 8 * (kMaxPieces + 1) + 256;
+                constexpr uint32_t rby_lds = 163840u / rlds;
+                constexpr uint32_t rby_waves = 32u / (RBD / 64);
+                constexpr uint32_t rocc = rby_lds < rby_waves ? rby_lds : rby_waves;
+                const uint32_t grid = min(a.stride, kNumCUs * (rocc ? rocc : 1u));
+                DS_LAUNCH("s89_gather_sort", (k_gather_radix<CAP, F32>), dim3(grid), dim3(RBD), a,
+                          I);
+            } else {
+                const uint32_t grid = min(a.stride, kNumCUs * (occ ? occ : 1u));
+                DS_LAUNCH("s89_gather_merge", (k_gather_merge<K, V, CAP, F32>), dim3(grid),
+                          dim3(BD), a, I);
+            }
+            return gather_classes<I + 1>(a, st, tm);
+        }
+        return DSORT_OK;
+    }
 
     // Step 4 for one level.  G > 0 segments sorted one workgroup each, or (global) the single
     // segment's m*s samples by chunk sorts plus merge rounds ending in `sorted`.
@@ -700,6 +1424,22 @@ template <class K, bool V, bool F32> struct Pipeline {
         return DSORT_OK;
     }
 
+    // Steps 1-3 with the radix tile kernel instantiated for the sublist length.
+    template <bool XIN>
+    static int tile_radix(const char *name, uint32_t L, uint32_t grid, const uint32_t *src,
+                          uint32_t *dst, SegView sv, uint32_t s, uint64_t *samples,
+                          hipStream_t st, Timing *tm) {
+        switch (L) {
+            case 1024: DS_LAUNCH(name, (k_tile_radix<XIN, 64>), dim3(grid), dim3(64), src, dst, sv, L, s, samples); break;
+            case 2048: DS_LAUNCH(name, (k_tile_radix<XIN, 128>), dim3(grid), dim3(128), src, dst, sv, L, s, samples); break;
+            case 4096: DS_LAUNCH(name, (k_tile_radix<XIN, 256>), dim3(grid), dim3(256), src, dst, sv, L, s, samples); break;
+            case 8192: DS_LAUNCH(name, (k_tile_radix<XIN, 512>), dim3(grid), dim3(512), src, dst, sv, L, s, samples); break;
+            case 16384: DS_LAUNCH(name, (k_tile_radix<XIN, 1024>), dim3(grid), dim3(1024), src, dst, sv, L, s, samples); break;
+            default: return DSORT_E_UNSUPPORTED;
+        }
+        return DSORT_OK;
+    }
+
     static int run(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, hipStream_t st,
                    Timing *tm) {
         char *ws = (char *)d_ws;
@@ -721,13 +1461,26 @@ template <class K, bool V, bool F32> struct Pipeline {
         SC *tmp = (SC *)(ws + g.o_samp_tmp);
         uint32_t *counts = (uint32_t *)(ws + g.o_counts);
         uint32_t *offs = (uint32_t *)(ws + g.o_offs);
-        uint2 *buckets1 = (uint2 *)(ws + g.o_buckets1);
+        uint32_t *pdst = (uint32_t *)(ws + g.o_pdst);
+        uint32_t *psrc = (uint32_t *)(ws + g.o_psrc);
+        uint32_t *partial = (uint32_t *)(ws + g.o_partial);
+        uint4 *buckets1 = (uint4 *)(ws + g.o_buckets1);
         uint32_t *tileoff2 = g.levels == 2 ? (uint32_t *)(ws + g.o_tileoff2) : nullptr;
         const SegView sv1{nullptr, nullptr, 1, n, n, g.m1};
+        // One level: the sorted sublists go to the workspace copy, and the fused Steps 8-9
+        // gather from there into keys.  Two levels: sorted in place, relocated into the copy.
+        K *tiles = g.levels == 1 ? wkeys : keys;
+        uint32_t *tvals = g.levels == 1 ? wvals : d_vals;
 
-        // Steps 1-3
-        {
-            TileArgs a{keys, keys, d_vals, d_vals, sv1, g.L1, g.s1, samp, status};
+        // Steps 1-3.  Full-range 32-bit sublists sort faster with the merge tile kernel (about
+        // 260 VALU instructions per key at full VALU issue) than with eight radix passes; the
+        // radix kernel serves sublists of one bucket, whose narrower key range needs fewer passes.
+        if (kRadix && kRadixLevel1 && g.L1 >= 1024) {
+            int rc0 = tile_radix<F32>("s123_local_sort", g.L1, g.m1, (const uint32_t *)keys,
+                                      (uint32_t *)tiles, sv1, g.s1, (uint64_t *)samp, st, tm);
+            if (rc0) return rc0;
+        } else {
+            TileArgs a{keys, tiles, d_vals, tvals, sv1, g.L1, g.s1, samp, status};
             DS_LAUNCH("s123_local_sort", (k_tile<K, V, TE, TCAP, MODE_SAMPLE, F32, false>),
                       dim3(g.m1), dim3(g.L1 / TE), a);
         }
@@ -737,44 +1490,46 @@ template <class K, bool V, bool F32> struct Pipeline {
                               "s4_sample_merge");
         if (rc) return rc;
         // Steps 5-6
-        DS_LAUNCH("s56_rank", (k_rank<K, V>), dim3(g.m1), dim3(256), (const K *)keys,
+        DS_LAUNCH("s56_rank", (k_rank<K, V>), dim3(g.m1), dim3(256), (const K *)tiles,
                   (const void *)sorted, counts, sv1, g.L1, g.s1);
         // Step 7
-        if (!g.scan_large) {
-            DS_LAUNCH("s7_scan", k_scan_small, dim3(1), dim3(256), (const uint32_t *)counts,
-                      offs, sv1, g.L1, g.s1, buckets1, tileoff2, g.L2);
-        } else {
-            uint32_t *partial = (uint32_t *)(ws + g.o_partial);
-            DS_LAUNCH("s7_scan_colsum", k_scan_partial, dim3(g.scan_nrb), dim3(256),
-                      (const uint32_t *)counts, partial, g.m1, g.s1, g.scan_rb);
-            DS_LAUNCH("s7_scan_mid", k_scan_mid, dim3(1), dim3(256), partial, g.scan_nrb, g.s1,
-                      n, buckets1, tileoff2, g.L2);
-            DS_LAUNCH("s7_scan_update", k_scan_apply, dim3(g.scan_nrb), dim3(256),
-                      (const uint32_t *)counts, (const uint32_t *)partial, offs, g.m1, g.s1,
-                      g.scan_rb);
+        DS_LAUNCH("s7_scan_colsum", k_scan_partial, dim3(g.scan_nrb), dim3(256),
+                  (const uint32_t *)counts, partial, g.m1, g.s1, g.scan_rb);
+        uint32_t *lists = (uint32_t *)(ws + g.o_lists);
+        const Classes cls = classes(status, lists, g.final_buckets);
+        Classes none{};
+        DS_LAUNCH("s7_scan_mid", k_scan_mid, dim3(1), dim3(256), partial, g.scan_nrb, g.m1, g.s1,
+                  n, buckets1, tileoff2, g.L2, g.levels == 1 ? cls : none);
+        DS_LAUNCH("s7_scan_update", k_scan_apply, dim3(g.scan_nrb), dim3(256),
+                  (const uint32_t *)counts, (const uint32_t *)partial, offs, pdst, psrc, g.m1,
+                  g.s1, g.scan_rb, g.L1);
+
+        if (g.levels == 1) {
+            // Steps 8-9 fused: gather every bucket's pieces, merge them, write into keys.
+            GatherArgs a{wkeys, keys, wvals, d_vals, buckets1, pdst, psrc, status + 1, lists,
+                         g.final_buckets, n, status};
+            return gather_classes<0>(a, st, tm);
         }
-        // Step 8
+
+        // Step 8 into the workspace copy, then Step 9 as a second level: Algorithm 1 on every
+        // bucket of level 1, with its own fused Steps 8-9 writing the final order into keys.
         DS_LAUNCH("s8_relocate", (k_relocate<K, V>), dim3(g.m1), dim3(256), (const K *)keys,
                   wkeys, (const uint32_t *)d_vals, wvals, (const uint32_t *)counts,
                   (const uint32_t *)offs, sv1, g.L1, g.s1);
-
-        if (g.levels == 1) {
-            // Step 9: every bucket in one workgroup, from the relocated copy back into keys.
-            TileArgs a{wkeys, keys, wvals, d_vals, SegView{buckets1, nullptr, g.s1, 0, n, 0}, 0,
-                       0, nullptr, status};
-            DS_LAUNCH("s9_bucket_sort", (k_tile<K, V, FE, FCAP, MODE_FINAL, false, F32>),
-                      dim3(g.s1), dim3(FCAP / FE), a);
-            return DSORT_OK;
-        }
-
-        // Step 9 as a second level: Algorithm 1 on every bucket of level 1.
         const SegView sv2{buckets1, tileoff2, g.s1, 0, n, g.tiles2max};
         SC *samp2 = (SC *)(ws + g.o_samp2);
         SC *sorted2 = (SC *)(ws + g.o_samp2_sorted);
         uint32_t *counts2 = (uint32_t *)(ws + g.o_counts2);
         uint32_t *offs2 = (uint32_t *)(ws + g.o_offs2);
-        uint2 *finals = (uint2 *)(ws + g.o_final);
-        {
+        uint32_t *pdst2 = (uint32_t *)(ws + g.o_pdst2);
+        uint32_t *psrc2 = (uint32_t *)(ws + g.o_psrc2);
+        uint4 *finals = (uint4 *)(ws + g.o_final);
+        if (kRadix && g.L2 >= 1024) {
+            int rc0 = tile_radix<false>("l2_s123_local_sort", g.L2, g.tiles2max,
+                                        (const uint32_t *)wkeys, (uint32_t *)wkeys, sv2, g.s2,
+                                        (uint64_t *)samp2, st, tm);
+            if (rc0) return rc0;
+        } else {
             TileArgs a{wkeys, wkeys, wvals, wvals, sv2, g.L2, g.s2, samp2, status};
             DS_LAUNCH("l2_s123_local_sort", (k_tile<K, V, TE, TCAP, MODE_SAMPLE, false, false>),
                       dim3(g.tiles2max), dim3(g.L2 / TE), a);
@@ -784,18 +1539,11 @@ template <class K, bool V, bool F32> struct Pipeline {
         if (rc) return rc;
         DS_LAUNCH("l2_s56_rank", (k_rank<K, V>), dim3(g.tiles2max), dim3(256), (const K *)wkeys,
                   (const void *)sorted2, counts2, sv2, g.L2, g.s2);
-        DS_LAUNCH("l2_s7_scan", k_scan_small, dim3(g.s1), dim3(256), (const uint32_t *)counts2,
-                  offs2, sv2, g.L2, g.s2, finals, (uint32_t *)nullptr, 0u);
-        DS_LAUNCH("l2_s8_relocate", (k_relocate<K, V>), dim3(g.tiles2max), dim3(256),
-                  (const K *)wkeys, keys, (const uint32_t *)wvals, d_vals,
-                  (const uint32_t *)counts2, (const uint32_t *)offs2, sv2, g.L2, g.s2);
-        {
-            TileArgs a{keys, keys, d_vals, d_vals, SegView{finals, nullptr, g.final_buckets, 0, n, 0},
-                       0, 0, nullptr, status};
-            DS_LAUNCH("s9_bucket_sort", (k_tile<K, V, FE, FCAP, MODE_FINAL, false, F32>),
-                      dim3(g.final_buckets), dim3(FCAP / FE), a);
-        }
-        return DSORT_OK;
+        DS_LAUNCH("l2_s7_scan", k_scan_seg, dim3(g.s1), dim3(256), (const uint32_t *)counts2,
+                  offs2, pdst2, psrc2, sv2, g.L2, g.s2, finals, cls);
+        GatherArgs a{wkeys, keys, wvals, d_vals, finals, pdst2, psrc2, status + 1, lists,
+                     g.final_buckets, n, status};
+        return gather_classes<0>(a, st, tm);
     }
 };
 
@@ -846,6 +1594,7 @@ int run_pipeline(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, void
                  Timing *tm) {
     hipStream_t st = (hipStream_t)stream;
     if (g.levels < 0) return DSORT_OK;
+    (void)hipGetLastError();  // do not attribute an earlier caller's error to this call
     if (g.n > 0xFFFFFFFFull) return DSORT_E_INVALID;
     if (tm && !tm->enabled) tm = nullptr;
     switch (g.key_type) {

@@ -9,6 +9,7 @@
 // sample set too large (more than 1/32 of the data), Step 9 instead runs Algorithm 1 again on
 // each bucket (a second level), whose buckets then fit one workgroup.
 #include <new>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -27,9 +28,10 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Largest bucket Step 8 can produce with m sublists of L items and s samples per sublist.
 uint64_t bucket_bound(uint64_t m, uint64_t L, uint64_t s) { return 2 * m * L / s - m; }
 
-constexpr uint32_t kScanSmallRows = 1024;  // one workgroup scans up to this many sublists
 constexpr uint32_t kScanRowBlock = 64;
 constexpr uint64_t kMaxSamples = 1024;  // per-sublist tables live in LDS
+constexpr uint64_t kMaxPieces = 256;    // pieces per bucket the fused Steps 8-9 accept
+constexpr uint64_t kNumClasses = 8;     // size classes of the fused Steps 8-9
 
 }  // namespace
 
@@ -95,7 +97,8 @@ int make_geom(int key_type, bool values, uint64_t n, const dsort_tuning_t &tu, G
     // --- one level: the smallest s whose bucket bound fits one workgroup.
     uint64_t s1 = 0;
     bool one = false;
-    if (tu.levels != 2) {
+    if (tu.levels == 1 && m1 > kMaxPieces) return DSORT_E_UNSUPPORTED;
+    if (tu.levels != 2 && m1 <= kMaxPieces) {
         if (tu.samples) {
             s1 = tu.samples;
             one = bucket_bound(m1, L1, s1) <= c.final_cap;
@@ -123,6 +126,7 @@ int make_geom(int key_type, bool values, uint64_t n, const dsort_tuning_t &tu, G
         for (uint64_t s = lo; s <= hi && !found; s <<= 1) {
             const uint64_t b1 = bucket_bound(m1, L1, s);
             const uint64_t mm = ceil_div(b1, L2);
+            if (mm > kMaxPieces) continue;
             const uint64_t t_lo = tu.samples2 ? tu.samples2 : 1;
             const uint64_t t_hi = tu.samples2 ? tu.samples2 : (L2 < kMaxSamples ? L2 : kMaxSamples);
             for (uint64_t t = t_lo; t <= t_hi; t <<= 1) {
@@ -148,7 +152,7 @@ int make_geom(int key_type, bool values, uint64_t n, const dsort_tuning_t &tu, G
         for (uint64_t run = c.samp_cap; run < sm; run <<= 1) ++r;
         g.samp_rounds = r;
     }
-    g.scan_large = m1 > kScanSmallRows;
+    g.scan_large = true;
     g.scan_rb = kScanRowBlock;
     g.scan_nrb = (uint32_t)ceil_div(m1, kScanRowBlock);
 
@@ -177,8 +181,10 @@ int make_geom(int key_type, bool values, uint64_t n, const dsort_tuning_t &tu, G
     if (g.samp_global) g.o_samp_tmp = take(sm * c.samp_bytes);
     g.o_counts = take(sm * 4);
     g.o_offs = take(sm * 4);
-    if (g.scan_large) g.o_partial = take((size_t)g.scan_nrb * s1 * 4);
-    g.o_buckets1 = take(s1 * 8);
+    g.o_pdst = take(sm * 4);
+    g.o_psrc = take(sm * 4);
+    g.o_partial = take((size_t)g.scan_nrb * s1 * 4);
+    g.o_buckets1 = take(s1 * 16);
     if (g.levels == 2) {
         g.o_tileoff2 = take((s1 + 1) * 4);
         const size_t sm2 = (size_t)g.tiles2max * s2;
@@ -186,12 +192,22 @@ int make_geom(int key_type, bool values, uint64_t n, const dsort_tuning_t &tu, G
         g.o_samp2_sorted = take(sm2 * c.samp_bytes);
         g.o_counts2 = take(sm2 * 4);
         g.o_offs2 = take(sm2 * 4);
-        g.o_final = take((size_t)g.final_buckets * 8);
+        g.o_pdst2 = take(sm2 * 4);
+        g.o_psrc2 = take(sm2 * 4);
+        g.o_final = take((size_t)g.final_buckets * 16);
     } else {
         g.o_final = g.o_buckets1;
     }
+    g.o_lists = take((size_t)kNumClasses * g.final_buckets * 4);
     g.total = off;
     return DSORT_OK;
+}
+
+static thread_local char g_last_error[256];
+
+void set_last_error(const char *stage, const char *name, const char *text) {
+    snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%s)", stage ? stage : "?",
+             name ? name : "?", text ? text : "?");
 }
 
 }  // namespace dsort
@@ -309,6 +325,8 @@ const char *dsort_strerror(int status) {
         default: return "unknown status";
     }
 }
+
+const char *dsort_last_error(void) { return dsort::g_last_error; }
 
 int dsort_plan_geometry(dsort_plan_t plan, uint64_t n, dsort_geometry_t *out) {
     if (!plan_ok(plan) || !out) return DSORT_E_INVALID;

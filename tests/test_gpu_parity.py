@@ -58,11 +58,12 @@ def check_level1(geo, ws, tr, n):
     assert (counts == tr.count).all(), "a_ij (Step 6)"
     offs = ws_view(ws, geo.off_offsets, m * s, np.uint32).reshape(m, s)
     assert (offs == tr.offset).all(), "l_ij (Step 7)"
-    b = ws_view(ws, geo.off_buckets, 2 * s, np.uint32).reshape(s, 2).astype(np.int64)
+    b = ws_view(ws, geo.off_buckets, 4 * s, np.uint32).reshape(s, 4).astype(np.int64)
     begin = tr.offset[0].astype(np.int64)
     real = np.clip(n - begin, 0, tr.bucket_size.astype(np.int64))
     assert (b[:, 0] == begin).all(), "bucket starts (Step 8)"
     assert (b[:, 1] == real).all(), "bucket sizes (Step 8)"
+    assert (b[:, 2] == np.arange(s) * m).all() and (b[:, 3] == m).all(), "bucket piece ranges"
 
 
 # ------------------------------------------------------------------ small, one tile
@@ -188,10 +189,10 @@ def test_u64_pairs_global_sample_sort(ds):
     say(f"u64 pairs global sample sort n={n}")
     keys = synth.zipf_u64(n, 53, distinct=1000)
     vals = synth.index_values(n)
-    tu = ds.Tuning(1024, 256, 0, 0, 1)
+    tu = ds.Tuning(2048, 256, 0, 0, 1)
     out_k, out_v, geo, ws = gpu_sort(ds, keys, vals, tuning=tu)
     assert geo.sample_sort_global
-    ok, ov, tr = oracle.dss(keys, 1024, 256, values=vals, trace=True)
+    ok, ov, tr = oracle.dss(keys, 2048, 256, values=vals, trace=True)
     assert (out_k == ok).all() and (out_v == ov).all()
     check_level1(geo, ws, tr, n)
 
