@@ -63,7 +63,7 @@ typedef struct dsort_plan_s *dsort_plan_t;
 
 /* Plan a sort of up to `max_items` items of key type `key_type` (DSORT_U32/U64/F32), with
  * (`with_values` = 1) or without (0) a uint32 value per key.  `max_segments` bounds the
- * segment count of dsort_segmented (0 if unused).  `tuning` may be NULL.
+ * segment count of dsort_segmented (0 if unused, at most 2^24).  `tuning` may be NULL.
  * On success *out receives the plan (host memory, owned by the caller until
  * dsort_plan_destroy) and *workspace_bytes the size of the device workspace every call
  * with this plan needs.  The plan holds host state only and allocates no device memory.
@@ -124,6 +124,52 @@ typedef struct {
 } dsort_geometry_t;
 
 int dsort_plan_geometry(dsort_plan_t plan, uint64_t n, dsort_geometry_t *out);
+
+/* Segmented sort: sorts each of `num_segments` segments of the n-item arrays on its own, in
+ * place, as if dsort_keys / dsort_pairs ran on each (same key order, same stability); one
+ * call sorts them all, so many small sorts share the device.  Segment g is the item range
+ * [d_offsets[g], d_offsets[g+1]) (CSR form: d_offsets is device memory holding num_segments + 1
+ * non-decreasing uint64 values, all <= n, read on the device).  Items outside every segment
+ * are left untouched.  d_values is NULL for keys-only plans and n uint32 values otherwise.
+ * `max_segment` is a bound on every segment's length (0 = the limit below, or n if smaller);
+ * it fixes the plan used for the long segments, so a tight bound saves work.
+ *
+ * Method (Algorithm 1 applied per segment, as in a second level of Step 9): a segment of at
+ * most `small_capacity` items is one bucket, sorted inside one workgroup; every longer segment
+ * runs one level of Algorithm 1 (sublists of L items, s samples per sublist, its own splitters
+ * and buckets), all segments together in the same kernel launches.  A segment may hold at most
+ * `segment_limit` items (dsort_segmented_geometry); longer ones need dsort_keys/dsort_pairs.
+ *
+ * The plan must have been made with max_segments >= num_segments and max_items >= n; the
+ * workspace is the plan's.  Bad offsets are caught on the device and reported in the uint32
+ * status word at workspace offset `off_status` (0 = clean run): offsets that decrease or
+ * exceed n set bit 16 and then no segment is sorted; a segment longer than max_segment sets
+ * bit 32 and is left as it is (the others are sorted).
+ * Errors: DSORT_E_INVALID (bad plan or pointer, misalignment, values given to a keys-only plan
+ * or missing for a pairs plan, n or num_segments above the plan's), DSORT_E_UNSUPPORTED
+ * (max_segment above segment_limit), DSORT_E_HIP.  n = 0 or num_segments = 0 is a no-op. */
+int dsort_segmented(dsort_plan_t plan, void *d_keys, uint32_t *d_values, uint64_t n,
+                    const uint64_t *d_offsets, uint64_t num_segments, uint64_t max_segment,
+                    void *d_workspace, void *stream);
+
+/* Geometry of a segmented call with these sizes (see dsort_segmented). */
+typedef struct {
+    uint64_t n, num_segments;
+    uint64_t max_segment;        /* the bound used (after defaulting and clamping to n) */
+    uint64_t segment_limit;      /* longest segment this key layout accepts */
+    uint32_t small_capacity;     /* segments up to this size are sorted in one workgroup */
+    uint32_t max_long_segments;  /* bound on segments longer than small_capacity */
+    uint32_t sublist_len;        /* L for long segments (0 if there can be none) */
+    uint32_t samples;            /* s for long segments */
+    uint32_t max_sublists;       /* bound on sublists over all long segments */
+    uint32_t reserved;
+    uint64_t bucket_bound;       /* largest bucket of the longest admissible segment */
+    uint64_t off_status;         /* uint32 error flags raised by kernels (0 = none) */
+    uint64_t workspace_bytes;    /* bytes these sizes need (<= the plan's workspace size) */
+} dsort_seg_geometry_t;
+
+int dsort_segmented_geometry(dsort_plan_t plan, uint64_t n, uint64_t num_segments,
+                             uint64_t max_segment, dsort_seg_geometry_t *out);
 
 /* Per-kernel timing, for profiling.  dsort_set_timing(plan, 1) clears the record and makes
  * every later sorting call on `plan` bracket each kernel launch with two HIP events recorded

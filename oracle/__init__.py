@@ -136,6 +136,26 @@ def stable_sort(keys: np.ndarray, values: np.ndarray | None = None):
     return out_k, out_v
 
 
+def segmented_sort(keys: np.ndarray, offsets, values: np.ndarray | None = None):
+    """A batch of independent sorts: segment g, the range [offsets[g], offsets[g+1]), is sorted
+    on its own by the plain definition (stable sort by key order, Algorithm 1's output applied
+    per segment); items outside every segment keep their places.  Offsets must be
+    non-decreasing and within the array."""
+    offsets = [int(x) for x in offsets]
+    out_k = np.array(keys, copy=True)
+    out_v = np.array(values, dtype=np.uint32, copy=True) if values is not None else None
+    for lo, hi in zip(offsets[:-1], offsets[1:]):
+        if not 0 <= lo <= hi <= keys.size:
+            raise ValueError(f"bad segment [{lo}, {hi})")
+        if hi - lo < 2:
+            continue
+        k, v = stable_sort(keys[lo:hi], None if values is None else values[lo:hi])
+        out_k[lo:hi] = k
+        if values is not None:
+            out_v[lo:hi] = v
+    return out_k, out_v
+
+
 def f32_order(bits: int) -> int:
     """totalOrder image of one binary32 bit pattern."""
     return int(_load().oracle_f32_order(bits))

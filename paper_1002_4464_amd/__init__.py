@@ -13,7 +13,7 @@ from dataclasses import dataclass
 
 __all__ = [
     "U32", "U64", "F32", "DsortError", "Tuning", "Plan", "load_library", "sort", "sort_pairs",
-    "strerror", "EXPORTED_SYMBOLS",
+    "sort_segmented", "strerror", "EXPORTED_SYMBOLS",
 ]
 
 U32, U64, F32 = 1, 2, 3
@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libdsort.so")
 EXPORTED_SYMBOLS = (
     "dsort_plan", "dsort_keys", "dsort_pairs", "dsort_plan_destroy", "dsort_strerror",
     "dsort_plan_geometry", "dsort_set_timing", "dsort_stage_times", "dsort_last_error",
+    "dsort_segmented", "dsort_segmented_geometry",
 )
 
 
@@ -53,6 +54,16 @@ class _Geometry(ctypes.Structure):
                 ("off_status", ctypes.c_uint64), ("off_samples", ctypes.c_uint64),
                 ("off_sorted_samples", ctypes.c_uint64), ("off_counts", ctypes.c_uint64),
                 ("off_offsets", ctypes.c_uint64), ("off_buckets", ctypes.c_uint64),
+                ("workspace_bytes", ctypes.c_uint64)]
+
+
+class _SegGeometry(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("num_segments", ctypes.c_uint64),
+                ("max_segment", ctypes.c_uint64), ("segment_limit", ctypes.c_uint64),
+                ("small_capacity", ctypes.c_uint32), ("max_long_segments", ctypes.c_uint32),
+                ("sublist_len", ctypes.c_uint32), ("samples", ctypes.c_uint32),
+                ("max_sublists", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("bucket_bound", ctypes.c_uint64), ("off_status", ctypes.c_uint64),
                 ("workspace_bytes", ctypes.c_uint64)]
 
 
@@ -95,6 +106,10 @@ def load_library(path: str = LIB_PATH):
                                       ctypes.POINTER(ctypes.c_float),
                                       ctypes.POINTER(ctypes.c_uint32), I, ctypes.POINTER(I)]
     lib.dsort_stage_times.restype = I
+    lib.dsort_segmented.argtypes = [P, P, P, U64_, P, U64_, U64_, P, P]
+    lib.dsort_segmented.restype = I
+    lib.dsort_segmented_geometry.argtypes = [P, U64_, U64_, U64_, ctypes.POINTER(_SegGeometry)]
+    lib.dsort_segmented_geometry.restype = I
     lib.dsort_last_error.argtypes = []
     lib.dsort_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -133,6 +148,23 @@ class Geometry:
     workspace_bytes: int
 
 
+@dataclass
+class SegGeometry:
+    n: int
+    num_segments: int
+    max_segment: int
+    segment_limit: int
+    small_capacity: int
+    max_long_segments: int
+    sublist_len: int
+    samples: int
+    max_sublists: int
+    reserved: int
+    bucket_bound: int
+    off_status: int
+    workspace_bytes: int
+
+
 class Plan:
     """A sort plan (host state) plus, on demand, a torch-allocated device workspace."""
 
@@ -143,6 +175,7 @@ class Plan:
         self.key_type = key_type
         self.values = bool(values)
         self.max_items = int(max_items)
+        self.max_segments = int(max_segments)
         h = ctypes.c_void_p()
         ws = ctypes.c_size_t()
         rc = lib.dsort_plan(ctypes.byref(h), key_type, int(self.values), self.max_items,
@@ -164,6 +197,13 @@ class Plan:
         _check(self._lib.dsort_plan_geometry(self._h, int(n), ctypes.byref(g)),
                "dsort_plan_geometry")
         return Geometry(*[getattr(g, f) for f, _ in _Geometry._fields_])
+
+    def segmented_geometry(self, n: int, num_segments: int, max_segment: int = 0) -> SegGeometry:
+        g = _SegGeometry()
+        _check(self._lib.dsort_segmented_geometry(self._h, int(n), int(num_segments),
+                                                  int(max_segment), ctypes.byref(g)),
+               "dsort_segmented_geometry")
+        return SegGeometry(*[getattr(g, f) for f, _ in _SegGeometry._fields_])
 
     def set_timing(self, enable: bool):
         """Bracket every kernel launch of later calls with HIP events (clears the record)."""
@@ -233,6 +273,31 @@ class Plan:
         _check(rc, "dsort_pairs")
         return keys, values
 
+    def sort_segmented(self, keys, offsets, values=None, max_segment: int = 0, workspace=None,
+                       stream=None):
+        """Sorts every segment [offsets[g], offsets[g+1]) of ``keys`` (and ``values``) in place.
+        ``offsets``: device tensor of S + 1 int64 (CSR form).  ``max_segment`` bounds the
+        segment lengths (0: the longest supported).  Returns keys (and values)."""
+        if (values is not None) != self.values:
+            raise ValueError("values must be given exactly for plans made with values")
+        ksz = 8 if self.key_type == U64 else 4
+        kp = self._dev_ptr(keys, ksz, "keys")
+        op = self._dev_ptr(offsets, 8, "offsets")
+        if offsets.numel() < 1:
+            raise ValueError("offsets needs S + 1 entries")
+        vp = None
+        if values is not None:
+            if values.numel() != keys.numel():
+                raise ValueError("keys and values differ in length")
+            vp = ctypes.c_void_p(self._dev_ptr(values, 4, "values"))
+        ws = workspace if workspace is not None else self.workspace(keys.device)
+        rc = self._lib.dsort_segmented(self._h, ctypes.c_void_p(kp), vp, keys.numel(),
+                                       ctypes.c_void_p(op), offsets.numel() - 1, int(max_segment),
+                                       ctypes.c_void_p(ws.data_ptr()),
+                                       self._stream(stream, keys.device))
+        _check(rc, "dsort_segmented")
+        return keys if values is None else (keys, values)
+
 
 def _key_type_of(t, key_type):
     if key_type is not None:
@@ -269,3 +334,19 @@ def sort_pairs(keys, values, key_type: int | None = None, stream=None):
     """Stable key/value sort in place; values are 4-byte elements."""
     kt = _key_type_of(keys, key_type)
     return _plan_for(kt, True, keys.numel()).sort_pairs(keys, values, stream=stream)
+
+
+def sort_segmented(keys, offsets, values=None, key_type: int | None = None, max_segment: int = 0,
+                   stream=None):
+    """Sorts each segment [offsets[g], offsets[g+1]) of a device tensor in place (key order as
+    for ``sort``; with ``values``, stable as for ``sort_pairs``).  ``offsets`` is a device
+    tensor of S + 1 int64 values."""
+    kt = _key_type_of(keys, key_type)
+    n = keys.numel()
+    S = offsets.numel() - 1
+    cap = 1 << max(10, (max(n, 2) - 1).bit_length())
+    scap = 1 << max(6, (max(S, 1) - 1).bit_length())
+    k = (kt, values is not None, cap, scap)
+    if k not in _plans:
+        _plans[k] = Plan(kt, values is not None, cap, max_segments=scap)
+    return _plans[k].sort_segmented(keys, offsets, values, max_segment=max_segment, stream=stream)

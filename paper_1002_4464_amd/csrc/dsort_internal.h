@@ -55,6 +55,30 @@ struct Geom {
     size_t total = 0;
 };
 
+// Geometry of a segmented sort: S segments over n items, none longer than max_seg.  Segments
+// of at most small_cap items are sorted as one-piece buckets; the (at most gmax) longer ones
+// run one level of Algorithm 1 with sublists of L items and s samples each.
+struct SegGeom {
+    int key_type = 0;
+    bool values = false;
+    uint64_t n = 0, S = 0, max_seg = 0;
+    Caps caps{};
+    uint32_t small_cap = 0;
+    uint32_t gmax = 0, L = 0, s = 0, tiles_max = 0;
+    uint64_t beta = 0;  // bucket bound of the longest admissible segment
+    size_t o_status = 0, o_segtab = 0, o_tileoff = 0, o_small_b = 0, o_spiece = 0, o_slists = 0;
+    size_t o_wkeys = 0, o_wvals = 0, o_samp = 0, o_samp_sorted = 0, o_counts = 0, o_offs = 0;
+    size_t o_pdst = 0, o_psrc = 0, o_final = 0, o_lists = 0;
+    size_t total = 0;
+};
+
+// Most segments one segmented call accepts (the set-up walks them in one workgroup).
+constexpr uint64_t kMaxSegments = 1u << 24;
+
+// Longest segment the one-level segmented plan accepts for this key layout.
+uint64_t seg_limit(int key_type, bool values);
+
+
 // Computes the geometry for n items.  Returns DSORT_OK or DSORT_E_UNSUPPORTED.
 int make_geom(int key_type, bool values, uint64_t n, const dsort_tuning_t &tuning, Geom &g);
 
@@ -79,6 +103,10 @@ int timing_summary(Timing &t, const char **names, float *avg_ms, uint32_t *launc
                    int capacity, int *count);
 
 // Enqueues the whole pipeline (kernels.hip).  Pointers are device pointers; tm may be null.
+int make_seg_geom(int key_type, bool values, uint64_t n, uint64_t S, uint64_t max_seg,
+                  SegGeom &g);
+int run_segmented(const SegGeom &g, void *d_keys, uint32_t *d_vals, const uint64_t *d_off,
+                  void *d_ws, void *stream, Timing *tm);
 int run_pipeline(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, void *stream,
                  Timing *tm);
 

@@ -23,6 +23,14 @@
 
 #include "dsort_internal.h"
 
+// Kernel selection knobs (both choices are bit-identical; they differ only in speed).
+#ifndef DSORT_BUCKET_SORT
+#define DSORT_BUCKET_SORT 0  // Steps 8-9: 0 = gather + merge sort, 1 = gather + radix sort
+#endif
+#ifndef DSORT_RADIX_L2
+#define DSORT_RADIX_L2 0     // level-2 sublists: 0 = merge tile sort, 1 = radix tile sort
+#endif
+
 namespace dsort {
 namespace {
 
@@ -271,10 +279,11 @@ __device__ __forceinline__ void serial_merge(const T *lds, uint32_t ai, uint32_t
     }
 }
 
-// Sorts lds[0, P) in place (P a power of two, E <= P <= E * blockDim.x; lds must hold
+// Sorts lds[0, P) in place (P a multiple of E, E <= P <= E * blockDim.x; lds must hold
 // lds_elems(P) + 1 elements, the last one only ever read speculatively).  Thread t owns
-// items [tE, tE+E): a register network sorts them, then log2(P/E) merge passes double the
-// sorted run length.  All threads of the block must call it.
+// items [tE, tE+E): a register network sorts them, then merge passes double the sorted run
+// length; when P is not a power of two the last run of a pass is shorter (or has no partner).
+// All threads of the block must call it.
 template <class T, int E> __device__ __forceinline__ void block_sort(T *lds, uint32_t P) {
     const uint32_t t = threadIdx.x;
     const bool act = t * E < P;
@@ -292,8 +301,11 @@ template <class T, int E> __device__ __forceinline__ void block_sort(T *lds, uin
             const uint32_t start = t * E;
             const uint32_t base = start & ~(2 * R - 1);
             const uint32_t diag = start - base;
-            const uint32_t a = merge_path<T>(lds, base, R, base + R, R, diag);
-            serial_merge_nc<T, E>(lds, base + a, base + R, base + R + diag - a, base + 2 * R, x);
+            const uint32_t na = min(R, P - base);
+            const uint32_t nb = min(R, P - base - na);
+            const uint32_t a = merge_path<T>(lds, base, na, base + na, nb, diag);
+            serial_merge_nc<T, E>(lds, base + a, base + na, base + na + diag - a, base + na + nb,
+                                  x);
         }
         __syncthreads();
         if (act) {
@@ -889,6 +901,7 @@ __global__ __launch_bounds__(256) void k_scan_seg(const uint32_t *counts, uint32
     if (sv.tile_off[g + 1] > sv.max_tiles) return;
     const uint32_t tile0 = sv.tile_off[g];
     const uint32_t m = sv.tile_off[g + 1] - tile0;
+    if (m == 0) return;  // no tiles: no buckets (they are never on a work list)
     const uint32_t seg_begin = sv.seg[g].x, seg_size = sv.seg[g].y;
     for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) {
         uint32_t sum = 0;
@@ -1083,6 +1096,13 @@ struct GatherArgs {
 };
 
 constexpr uint32_t kMaxPieces = 256;
+
+// Items per thread of the merge-sort bucket kernel: 16 (8 for 16-byte elements), raised so that
+// CAP / E <= 1024 threads.
+template <class K, bool V, int CAP> struct GatherE {
+    static constexpr int base = sizeof(typename Tr<K, V>::T) >= 16 ? 8 : 16;
+    static constexpr int E = CAP / base > 1024 ? CAP / 1024 : base;
+};
 constexpr int kGatherE = 16;
 
 // Threads and chunks per thread of the class holding CAP items: enough chunk slots for
@@ -1272,10 +1292,181 @@ __global__ __launch_bounds__(CAP / 16) __attribute__((amdgpu_waves_per_eu(8))) v
     }
 }
 
+// Steps 8 and 9 fused, merge-sort flavour: the pieces of a bucket are gathered into LDS as
+// above (with their bucket positions as tie-breaks for key/value sorts), padded with key-max
+// items to a multiple of E, and sorted with the block merge sort.  One workgroup of CAP / E
+// threads per bucket of at most CAP items; persistent over the class's work list.
+template <class K, bool V, int CAP, bool XOUT, bool XIN = false>
+__global__ __launch_bounds__((CAP / GatherE<K, V, CAP>::E))
+    void k_gather_bsort(GatherArgs a, uint32_t cls) {
+    using R = Tr<K, V>;
+    using T = typename R::T;
+    constexpr int E = GatherE<K, V, CAP>::E;
+    constexpr uint32_t BD = CAP / E;
+    __shared__ T lds[lds_elems<T>(CAP) + 1];
+    __shared__ uint32_t bnd[kMaxPieces + 1], ps[kMaxPieces];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63, w = tid >> 6, nw = BD >> 6;
+    const uint32_t nwork = min(a.count[cls], a.stride);
+    const uint32_t *list = a.list + (size_t)cls * a.stride;
+    const K *src = (const K *)a.src_keys;
+    K *dst = (K *)a.dst_keys;
+    for (uint32_t item = blockIdx.x; item < nwork; item += gridDim.x) {
+        const uint4 b = a.buckets[list[item]];
+        const uint32_t begin = b.x, total = b.y, pbase = b.z, np = b.w;
+        if (total == 0 || total > CAP || np > kMaxPieces || np == 0 ||
+            (uint64_t)begin + total > a.n_total) {
+            if (tid == 0) atomicOr(a.status, 8u);
+            continue;
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < np; i += BD) {
+            bnd[i] = min(a.pdst[pbase + i] - begin, total);
+            ps[i] = a.psrc[pbase + i];
+        }
+        if (tid == 0) bnd[np] = total;
+        __syncthreads();
+        const uint32_t P = (total + E - 1) / E * E;
+        const uint32_t span = ((P + nw - 1) / nw + 63) & ~63u;
+        const uint32_t x_begin = w * span, x_end = min(P, x_begin + span);
+        if (x_begin < x_end) {
+            uint32_t p = 0;
+            {
+                uint32_t lo = 0, hi = np - 1;
+                const uint32_t xs = min(x_begin + lane, total - 1);
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi + 1) >> 1;
+                    if (bnd[mid] <= xs) lo = mid; else hi = mid - 1;
+                }
+                p = lo;
+            }
+            for (uint32_t row = x_begin; row < x_end; row += 4 * 64) {
+                K v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t xu = row + 64 * u + lane;
+                    if (xu < total) {
+                        while (xu >= bnd[p + 1]) ++p;
+                        v[u] = src[ps[p] + (xu - bnd[p])];
+                        if (XIN) v[u] = (K)f32_in((uint32_t)v[u]);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t xu = row + 64 * u + lane;
+                    if (xu < x_end) lds[pidx<T>(xu)] = xu < total ? R::make(v[u], xu) : R::pad(xu);
+                }
+            }
+        }
+        __syncthreads();
+        block_sort<T, E>(lds, P);
+
+        uint32_t pos[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const uint32_t x = tid + q * BD;
+            if (x < total) {
+                const T el = lds[pidx<T>(x)];
+                K kk = R::key(el);
+                if (XOUT) kk = (K)f32_out((uint32_t)kk);
+                dst[begin + x] = kk;
+                pos[q] = R::lpos(el);
+            }
+        }
+        if (V) {
+            __syncthreads();
+            uint32_t *lv = (uint32_t *)lds;
+            for (uint32_t i = w; i < np; i += nw) {
+                const uint32_t d0 = bnd[i], len = bnd[i + 1] - d0, s0 = ps[i];
+                for (uint32_t q = lane; q < len; q += 64) lv[d0 + q] = a.src_vals[s0 + q];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                const uint32_t x = tid + q * BD;
+                if (x < total) a.dst_vals[begin + x] = lv[pos[q]];
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------------------ misc
 
 __global__ void k_init(uint32_t *status) {
-    if (threadIdx.x <= (uint32_t)kMaxClasses && blockIdx.x == 0) status[threadIdx.x] = 0;
+    if (threadIdx.x <= 2u * kMaxClasses && blockIdx.x == 0) status[threadIdx.x] = 0;
+}
+
+// Segmented sort set-up, one workgroup.  From the caller's CSR offsets (S + 1 uint64):
+//  * every segment that fits one workgroup (0 < size <= small_cap) becomes a one-piece bucket
+//    {begin, size, g, 1} on the work list of its size class;
+//  * the longer ones, in input order, form the compact segment table `large_tab` (at most gmax
+//    entries) and its tile map `tile_off` (ceil(size / L) tiles each, exclusive prefix); the
+//    unused entries up to gmax are empty segments with no tiles.
+// Offsets that decrease or pass n would let segments overlap or leave the array: then no
+// segment is sorted and status bit 16 is set.  A segment longer than max_seg is left as it is
+// and sets bit 32.
+__global__ __launch_bounds__(1024) void k_seg_prepare(const uint64_t *off, uint32_t S, uint32_t n,
+                                                      uint32_t max_seg, uint32_t L,
+                                                      uint32_t small_cap, uint32_t gmax,
+                                                      uint4 *large_tab, uint32_t *tile_off,
+                                                      uint4 *small_b, uint32_t *spiece,
+                                                      Classes cls, uint32_t *status) {
+    __shared__ uint32_t wsum[17];
+    __shared__ uint32_t carry_t, carry_g, malformed;
+    if (threadIdx.x == 0) {
+        carry_t = carry_g = 0;
+        malformed = off[S] > n ? 1u : 0u;
+    }
+    __syncthreads();
+    for (uint32_t g = threadIdx.x; g < S; g += blockDim.x)
+        if (off[g + 1] < off[g]) malformed = 1u;
+    __syncthreads();
+    const bool skip_all = malformed != 0;
+    if (skip_all && threadIdx.x == 0) atomicOr(status, 16u);
+    for (uint32_t b0 = 0; b0 < S; b0 += blockDim.x) {
+        const uint32_t g = b0 + threadIdx.x;
+        uint32_t begin = 0, size = 0;
+        if (g < S && !skip_all) {
+            const uint64_t lo = off[g], hi = off[g + 1];
+            if (hi - lo > max_seg) {
+                atomicOr(status, 32u);
+            } else {
+                begin = (uint32_t)lo;
+                size = (uint32_t)(hi - lo);
+            }
+            if (size > 0 && size <= small_cap) {
+                small_b[g] = make_uint4(begin, size, g, 1u);
+                spiece[g] = begin;
+                uint32_t c = 0;
+                while (c + 1 < cls.n && cls.cap[c] < size) ++c;
+                const uint32_t at = atomicAdd(&cls.count[c], 1u);
+                if (at < cls.stride) cls.list[(size_t)c * cls.stride + at] = g;
+            }
+        }
+        bool large = size > small_cap;
+        uint32_t tot_t, tot_g;
+        const uint32_t ex_g = block_excl_scan(large ? 1u : 0u, wsum, tot_g);
+        const uint32_t idx = carry_g + ex_g;
+        if (large && idx >= gmax) {  // cannot happen for disjoint segments inside [0, n)
+            atomicOr(status, 16u);
+            large = false;
+        }
+        const uint32_t ex_t = block_excl_scan(large ? (size + L - 1) / L : 0u, wsum, tot_t);
+        if (large) {
+            large_tab[idx] = make_uint4(begin, size, 0u, 0u);
+            tile_off[idx] = carry_t + ex_t;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            carry_t += tot_t;
+            carry_g = min(carry_g + tot_g, gmax);
+        }
+        __syncthreads();
+    }
+    for (uint32_t i = carry_g + threadIdx.x; i <= gmax; i += blockDim.x) {
+        tile_off[i] = carry_t;
+        if (i < gmax) large_tab[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
 }
 
 // ------------------------------------------------------------------------------ host driver
@@ -1357,6 +1548,9 @@ template <class K, bool V, bool F32> struct Pipeline {
     // 32-bit keys without values use the radix local sorts; other layouts the merge sorts.
     static constexpr bool kRadix = !V && sizeof(K) == 4;
     static constexpr bool kRadixLevel1 = false;
+    static constexpr bool kRadixLevel2 = DSORT_RADIX_L2 != 0;
+    // Steps 8-9: gather + block merge sort (default), or the radix / run-merge kernels.
+    static constexpr bool kBucketMerge = DSORT_BUCKET_SORT == 0;
     static_assert(CC::cap[CC::n - 1] == (uint32_t)FCAP, "last class must be the bucket capacity");
 
     static Classes classes(uint32_t *status, uint32_t *lists, uint32_t stride) {
@@ -1370,16 +1564,22 @@ template <class K, bool V, bool F32> struct Pipeline {
     }
 
     // One persistent launch per size class, each sized to fill the chip at its occupancy.
-    template <uint32_t I>
+    template <uint32_t I, bool XIN = false>
     static int gather_classes(const GatherArgs &a, hipStream_t st, Timing *tm) {
+        static_assert(!XIN || kBucketMerge, "f32 input on the gather needs the merge kernel");
         if constexpr (I < CC::n) {
             constexpr int CAP = (int)CC::cap[I];
-            constexpr uint32_t BD = GatherShape<CAP>::BD;
-            constexpr uint32_t lds = lds_elems<T>(CAP) * sizeof(T) + 8 * (kMaxPieces + 1);
-            constexpr uint32_t by_lds = 163840u / lds;
-            constexpr uint32_t by_waves = 32u / (BD / 64);
-            constexpr uint32_t occ = by_lds < by_waves ? by_lds : by_waves;
-            if constexpr (kRadix && CAP <= 16384) {
+            if constexpr (kBucketMerge) {
+                constexpr int GE = GatherE<K, V, CAP>::E;
+                constexpr uint32_t GBD = CAP / GE;
+                constexpr uint32_t glds = (lds_elems<T>(CAP) + 1) * sizeof(T) + 8 * (kMaxPieces + 1);
+                constexpr uint32_t gby_lds = 163840u / glds;
+                constexpr uint32_t gby_waves = 32u / ((GBD + 63) / 64);
+                constexpr uint32_t gocc = gby_lds < gby_waves ? gby_lds : gby_waves;
+                const uint32_t grid = min(a.stride, kNumCUs * (gocc ? gocc : 1u));
+                DS_LAUNCH("s89_gather_sort", (k_gather_bsort<K, V, CAP, F32, XIN>), dim3(grid),
+                          dim3(GBD), a, I);
+            } else if constexpr (kRadix && CAP <= 16384) {
                 constexpr uint32_t RBD = CAP / 16;
                 constexpr uint32_t rlds = lds_elems<uint32_t>(CAP) * 4 + 8 * (kMaxPieces + 1) + 256;
                 constexpr uint32_t rby_lds = 163840u / rlds;
@@ -1389,11 +1589,16 @@ template <class K, bool V, bool F32> struct Pipeline {
                 DS_LAUNCH("s89_gather_sort", (k_gather_radix<CAP, F32>), dim3(grid), dim3(RBD), a,
                           I);
             } else {
+                constexpr uint32_t BD = GatherShape<CAP>::BD;
+                constexpr uint32_t lds = lds_elems<T>(CAP) * sizeof(T) + 8 * (kMaxPieces + 1);
+                constexpr uint32_t by_lds = 163840u / lds;
+                constexpr uint32_t by_waves = 32u / (BD / 64);
+                constexpr uint32_t occ = by_lds < by_waves ? by_lds : by_waves;
                 const uint32_t grid = min(a.stride, kNumCUs * (occ ? occ : 1u));
                 DS_LAUNCH("s89_gather_merge", (k_gather_merge<K, V, CAP, F32>), dim3(grid),
                           dim3(BD), a, I);
             }
-            return gather_classes<I + 1>(a, st, tm);
+            return gather_classes<I + 1, XIN>(a, st, tm);
         }
         return DSORT_OK;
     }
@@ -1438,6 +1643,64 @@ template <class K, bool V, bool F32> struct Pipeline {
             default: return DSORT_E_UNSUPPORTED;
         }
         return DSORT_OK;
+    }
+
+    // Segmented sort: every segment [off[g], off[g+1]) sorted on its own.  Segments that fit a
+    // bucket workgroup are sorted in place as one-piece buckets; the others run one level of
+    // Algorithm 1 together (the segmented kernels of the second level), sublists sorted into the
+    // workspace copy and gathered back per bucket.
+    static int run_segmented(const SegGeom &g, void *d_keys, uint32_t *d_vals,
+                             const uint64_t *d_off, void *d_ws, hipStream_t st, Timing *tm) {
+        char *ws = (char *)d_ws;
+        uint32_t *status = (uint32_t *)(ws + g.o_status);
+        DS_LAUNCH("init", k_init, dim3(1), dim3(64), status);
+        K *keys = (K *)d_keys;
+        const uint32_t n = (uint32_t)g.n;
+        const uint32_t S = (uint32_t)g.S;
+        uint4 *large_tab = (uint4 *)(ws + g.o_segtab);
+        uint32_t *tile_off = (uint32_t *)(ws + g.o_tileoff);
+        uint4 *small_b = (uint4 *)(ws + g.o_small_b);
+        uint32_t *spiece = (uint32_t *)(ws + g.o_spiece);
+        uint32_t *slists = (uint32_t *)(ws + g.o_slists);
+        // counters of the one-piece classes follow those of the final buckets
+        const Classes scls = classes(status + kMaxClasses, slists, S);
+        DS_LAUNCH("seg_prepare", k_seg_prepare, dim3(1), dim3(1024), d_off, S, n,
+                  (uint32_t)g.max_seg, g.L, g.small_cap, g.gmax, large_tab, tile_off, small_b,
+                  spiece, scls, status);
+        {  // one-piece buckets in place: a workgroup reads its whole segment before writing
+            GatherArgs a{keys, keys, d_vals, d_vals, small_b, spiece, spiece, scls.count, slists,
+                         S, n, status};
+            int rc0 = gather_classes<0, F32>(a, st, tm);
+            if (rc0) return rc0;
+        }
+        if (!g.gmax) return DSORT_OK;
+        K *wkeys = (K *)(ws + g.o_wkeys);
+        uint32_t *wvals = V ? (uint32_t *)(ws + g.o_wvals) : nullptr;
+        SC *samp = (SC *)(ws + g.o_samp);
+        SC *sorted = (SC *)(ws + g.o_samp_sorted);
+        uint32_t *counts = (uint32_t *)(ws + g.o_counts);
+        uint32_t *offs = (uint32_t *)(ws + g.o_offs);
+        uint32_t *pdst = (uint32_t *)(ws + g.o_pdst);
+        uint32_t *psrc = (uint32_t *)(ws + g.o_psrc);
+        uint4 *finals = (uint4 *)(ws + g.o_final);
+        uint32_t *lists = (uint32_t *)(ws + g.o_lists);
+        const Classes cls = classes(status, lists, g.gmax * g.s);
+        const SegView sv{large_tab, tile_off, g.gmax, 0, n, g.tiles_max};
+        {
+            TileArgs a{keys, wkeys, d_vals, wvals, sv, g.L, g.s, samp, status};
+            DS_LAUNCH("s123_local_sort", (k_tile<K, V, TE, TCAP, MODE_SAMPLE, F32, false>),
+                      dim3(g.tiles_max), dim3(g.L / TE), a);
+        }
+        int rc = sort_samples(samp, sorted, nullptr, sv, g.L, g.s, g.gmax, 0, status, st, false,
+                              0, tm, "s4_sample_sort", "s4_sample_merge");
+        if (rc) return rc;
+        DS_LAUNCH("s56_rank", (k_rank<K, V>), dim3(g.tiles_max), dim3(256), (const K *)wkeys,
+                  (const void *)sorted, counts, sv, g.L, g.s);
+        DS_LAUNCH("s7_scan", k_scan_seg, dim3(g.gmax), dim3(256), (const uint32_t *)counts, offs,
+                  pdst, psrc, sv, g.L, g.s, finals, cls);
+        GatherArgs a{wkeys, keys, wvals, d_vals, finals, pdst, psrc, cls.count, lists,
+                     g.gmax * g.s, n, status};
+        return gather_classes<0>(a, st, tm);
     }
 
     static int run(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, hipStream_t st,
@@ -1524,7 +1787,7 @@ template <class K, bool V, bool F32> struct Pipeline {
         uint32_t *pdst2 = (uint32_t *)(ws + g.o_pdst2);
         uint32_t *psrc2 = (uint32_t *)(ws + g.o_psrc2);
         uint4 *finals = (uint4 *)(ws + g.o_final);
-        if (kRadix && g.L2 >= 1024) {
+        if (kRadix && kRadixLevel2 && g.L2 >= 1024) {
             int rc0 = tile_radix<false>("l2_s123_local_sort", g.L2, g.tiles2max,
                                         (const uint32_t *)wkeys, (uint32_t *)wkeys, sv2, g.s2,
                                         (uint64_t *)samp2, st, tm);
@@ -1588,6 +1851,30 @@ int timing_summary(Timing &t, const char **names, float *avg_ms, uint32_t *launc
     }
     *count = c;
     return DSORT_OK;
+}
+
+int run_segmented(const SegGeom &g, void *d_keys, uint32_t *d_vals, const uint64_t *d_off,
+                  void *d_ws, void *stream, Timing *tm) {
+    hipStream_t st = (hipStream_t)stream;
+    if (g.S == 0 || g.n == 0) return DSORT_OK;
+    (void)hipGetLastError();
+    if (tm && !tm->enabled) tm = nullptr;
+    switch (g.key_type) {
+        case DSORT_U32:
+            return g.values
+                ? Pipeline<uint32_t, true, false>::run_segmented(g, d_keys, d_vals, d_off, d_ws, st, tm)
+                : Pipeline<uint32_t, false, false>::run_segmented(g, d_keys, d_vals, d_off, d_ws, st, tm);
+        case DSORT_F32:
+            return g.values
+                ? Pipeline<uint32_t, true, true>::run_segmented(g, d_keys, d_vals, d_off, d_ws, st, tm)
+                : Pipeline<uint32_t, false, true>::run_segmented(g, d_keys, d_vals, d_off, d_ws, st, tm);
+        case DSORT_U64:
+            return g.values
+                ? Pipeline<uint64_t, true, false>::run_segmented(g, d_keys, d_vals, d_off, d_ws, st, tm)
+                : Pipeline<uint64_t, false, false>::run_segmented(g, d_keys, d_vals, d_off, d_ws, st, tm);
+        default:
+            return DSORT_E_INVALID;
+    }
 }
 
 int run_pipeline(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, void *stream,

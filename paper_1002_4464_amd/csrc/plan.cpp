@@ -203,6 +203,81 @@ int make_geom(int key_type, bool values, uint64_t n, const dsort_tuning_t &tu, G
     return DSORT_OK;
 }
 
+// Segmented sorts (one level).  A segment of z > small_cap items has m = ceil(z/L) sublists;
+// its s must keep every bucket within one workgroup (m (2L/s - 1) <= final_cap) and its m*s
+// samples within the one-workgroup sample sort (<= samp_cap).  Returns 0 if no s works.
+static uint64_t seg_samples(const Caps &c, uint64_t m) {
+    if (m > kMaxPieces) return 0;
+    const uint64_t L = c.tile_max;
+    for (uint64_t s = 1; s <= L && s <= kMaxSamples; s <<= 1)
+        if (bucket_bound(m, L, s) <= c.final_cap) return m * s <= c.samp_cap ? s : 0;
+    return 0;
+}
+
+uint64_t seg_limit(int key_type, bool values) {
+    const Caps c = caps_for(key_type, values);
+    uint64_t m = 1;
+    while (m < kMaxPieces && seg_samples(c, m + 1)) ++m;
+    const uint64_t lim = seg_samples(c, m) ? m * c.tile_max : 0;
+    return lim > c.final_cap ? lim : c.final_cap;
+}
+
+int make_seg_geom(int key_type, bool values, uint64_t n, uint64_t S, uint64_t max_seg,
+                  SegGeom &g) {
+    g = SegGeom{};
+    g.key_type = key_type;
+    g.values = values;
+    g.n = n;
+    g.S = S;
+    g.caps = caps_for(key_type, values);
+    const Caps &c = g.caps;
+    if (n > kMaxItems) return DSORT_E_INVALID;
+    const uint64_t lim = seg_limit(key_type, values);
+    if (max_seg == 0) max_seg = n < lim ? n : lim;
+    if (max_seg > n) max_seg = n;
+    if (max_seg > lim) return DSORT_E_UNSUPPORTED;
+    g.max_seg = max_seg;
+    g.small_cap = c.final_cap;
+    g.L = c.tile_max;
+    if (max_seg > g.small_cap) {
+        const uint64_t m = ceil_div(max_seg, g.L);
+        const uint64_t s = seg_samples(c, m);
+        if (!s) return DSORT_E_UNSUPPORTED;
+        g.s = (uint32_t)s;
+        g.beta = bucket_bound(m, g.L, s);
+        const uint64_t by_size = n / (g.small_cap + 1);
+        g.gmax = (uint32_t)(S < by_size ? S : by_size);
+        g.tiles_max = (uint32_t)(ceil_div(n, g.L) + g.gmax);
+    }
+    size_t off = 256;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    g.o_status = 0;
+    g.o_small_b = take(S * 16);
+    g.o_spiece = take(S * 4);
+    g.o_slists = take(kNumClasses * S * 4);
+    g.o_segtab = take((size_t)g.gmax * 16);
+    g.o_tileoff = take(((size_t)g.gmax + 1) * 4);
+    if (g.gmax) {
+        const size_t sm = (size_t)g.tiles_max * g.s;
+        g.o_wkeys = take(n * c.key_bytes);
+        if (values) g.o_wvals = take(n * 4);
+        g.o_samp = take(sm * c.samp_bytes);
+        g.o_samp_sorted = take(sm * c.samp_bytes);
+        g.o_counts = take(sm * 4);
+        g.o_offs = take(sm * 4);
+        g.o_pdst = take(sm * 4);
+        g.o_psrc = take(sm * 4);
+        g.o_final = take((size_t)g.gmax * g.s * 16);
+        g.o_lists = take(kNumClasses * (size_t)g.gmax * g.s * 4);
+    }
+    g.total = off;
+    return DSORT_OK;
+}
+
 static thread_local char g_last_error[256];
 
 void set_last_error(const char *stage, const char *name, const char *text) {
@@ -253,6 +328,7 @@ int dsort_plan(dsort_plan_t *out, int key_type, int with_values, uint64_t max_it
         return DSORT_E_INVALID;
     if (with_values != 0 && with_values != 1) return DSORT_E_INVALID;
     if (max_items > dsort::kMaxItems) return DSORT_E_INVALID;
+    if (max_segments > dsort::kMaxSegments) return DSORT_E_INVALID;
     dsort_tuning_t tu{};
     if (tuning) tu = *tuning;
     // The workspace must serve every n <= max_items.  The geometry is piecewise in n: on each
@@ -288,6 +364,15 @@ int dsort_plan(dsort_plan_t *out, int key_type, int with_values, uint64_t max_it
             if (e.total > ws) ws = e.total;
             lo = a + 1;
         }
+    }
+    // Segmented calls: every buffer grows with n, S and the longest admissible segment.
+    if (max_segments && max_items) {
+        const uint64_t lim = dsort::seg_limit(key_type, with_values != 0);
+        dsort::SegGeom sg;
+        if (dsort::make_seg_geom(key_type, with_values != 0, max_items, max_segments,
+                                 max_items < lim ? max_items : lim, sg) != DSORT_OK)
+            return DSORT_E_UNSUPPORTED;
+        if (sg.total > ws) ws = sg.total;
     }
     dsort_plan_s *p = new (std::nothrow) dsort_plan_s{};
     if (!p) return DSORT_E_NOMEM;
@@ -385,6 +470,55 @@ int dsort_stage_times(dsort_plan_t plan, const char **names, float *avg_ms, uint
                       int capacity, int *count) {
     if (!plan_ok(plan) || !count || capacity < 0) return DSORT_E_INVALID;
     return dsort::timing_summary(plan->timing, names, avg_ms, launches, capacity, count);
+}
+
+static int seg_geom_for(dsort_plan_t plan, uint64_t n, uint64_t S, uint64_t max_segment,
+                        dsort::SegGeom &g) {
+    if (!plan_ok(plan)) return DSORT_E_INVALID;
+    if (n > plan->max_items || S > plan->max_segments) return DSORT_E_INVALID;
+    return dsort::make_seg_geom(plan->key_type, plan->values != 0, n, S, max_segment, g);
+}
+
+int dsort_segmented_geometry(dsort_plan_t plan, uint64_t n, uint64_t num_segments,
+                             uint64_t max_segment, dsort_seg_geometry_t *out) {
+    if (!out) return DSORT_E_INVALID;
+    dsort::SegGeom g;
+    int rc = seg_geom_for(plan, n, num_segments, max_segment, g);
+    if (rc != DSORT_OK) return rc;
+    memset(out, 0, sizeof(*out));
+    out->n = n;
+    out->num_segments = num_segments;
+    out->max_segment = g.max_seg;
+    out->segment_limit = dsort::seg_limit(plan->key_type, plan->values != 0);
+    out->small_capacity = g.small_cap;
+    out->max_long_segments = g.gmax;
+    out->sublist_len = g.L;
+    out->samples = g.s;
+    out->max_sublists = g.tiles_max;
+    out->bucket_bound = g.beta;
+    out->off_status = g.o_status;
+    out->workspace_bytes = g.total;
+    return DSORT_OK;
+}
+
+int dsort_segmented(dsort_plan_t plan, void *d_keys, uint32_t *d_values, uint64_t n,
+                    const uint64_t *d_offsets, uint64_t num_segments, uint64_t max_segment,
+                    void *d_workspace, void *stream) {
+    if (!plan_ok(plan)) return DSORT_E_INVALID;
+    if ((plan->values != 0) != (d_values != nullptr)) return DSORT_E_INVALID;
+    if (n > plan->max_items || num_segments > plan->max_segments) return DSORT_E_INVALID;
+    if (n == 0 || num_segments == 0) return DSORT_OK;
+    if (!d_keys || !d_offsets || !d_workspace) return DSORT_E_INVALID;
+    if (((uintptr_t)d_workspace & 255) != 0 || ((uintptr_t)d_offsets & 7) != 0)
+        return DSORT_E_INVALID;
+    if (((uintptr_t)d_keys & (plan->key_type == DSORT_U64 ? 7 : 3)) != 0) return DSORT_E_INVALID;
+    if (d_values && ((uintptr_t)d_values & 3) != 0) return DSORT_E_INVALID;
+    dsort::SegGeom g;
+    int rc = seg_geom_for(plan, n, num_segments, max_segment, g);
+    if (rc != DSORT_OK) return rc;
+    if (g.total > plan->workspace) return DSORT_E_CAPACITY;
+    return dsort::run_segmented(g, d_keys, d_values, d_offsets, d_workspace, stream,
+                                &plan->timing);
 }
 
 int dsort_keys(dsort_plan_t plan, void *d_keys, uint64_t n, void *d_workspace, void *stream) {

@@ -114,3 +114,60 @@ def test_workspace_covers_all_smaller_sizes():
         p = ds.Plan(kt, values, 3_000_000)
         for n in list(range(2, 70_000, 997)) + list(range(70_000, 3_000_000, 29_989)):
             assert p.geometry(n).workspace_bytes <= p.workspace_bytes
+
+
+@pytest.mark.parametrize("kt,values", [(1, False), (1, True), (2, False), (2, True), (3, False)])
+def test_segmented_geometry_invariants(kt, values):
+    """Long segments run one level of Algorithm 1: for the longest admissible segment (m
+    sublists) the bucket bound m(2L/s - 1) fits one workgroup and the m*s samples fit the
+    one-workgroup sample sort; the plan's workspace covers every smaller batch."""
+    n = 1 << 24
+    p = ds.Plan(kt, values, n, max_segments=4096)
+    lim = p.segmented_geometry(n, 4096).segment_limit
+    assert lim >= 1 << 19
+    for S in [1, 17, 4096]:
+        for max_seg in [0, 1, 100, 8192, 8193, 16385, 32769, 100_000, lim]:
+            g = p.segmented_geometry(n, S, max_seg)
+            assert g.workspace_bytes <= p.workspace_bytes
+            assert g.max_segment == (min(n, lim) if max_seg == 0 else max_seg)
+            if g.max_segment <= g.small_capacity:
+                assert g.max_long_segments == 0
+                continue
+            L, s = g.sublist_len, g.samples
+            m = -(-g.max_segment // L)
+            assert g.bucket_bound == m * (2 * L // s - 1) <= g.small_capacity
+            assert s == 1 or m * (2 * L // (s // 2) - 1) > g.small_capacity or \
+                m * s > 8192  # s is the smallest that works, unless the samples cap binds
+            assert g.max_long_segments == min(S, n // (g.small_capacity + 1))
+            assert g.max_sublists >= -(-n // L)
+    with pytest.raises(ds.DsortError) as e:
+        p.segmented_geometry(n, 10, lim + 1)
+    assert e.value.status == ds.E_UNSUPPORTED
+    with pytest.raises(ds.DsortError) as e:
+        p.segmented_geometry(n, 4097, 0)
+    assert e.value.status == ds.E_INVALID
+
+
+def test_segmented_rejects_bad_arguments_without_gpu():
+    lib = ds.load_library()
+    p = ds.Plan(ds.U32, False, 1000, max_segments=8)
+    fake = ctypes.c_void_p(0x10000)
+    offs = ctypes.c_void_p(0x30000)
+    ws = ctypes.c_void_p(0x20000)
+    seg = lib.dsort_segmented
+    assert seg(p._h, fake, None, 1001, offs, 8, 0, ws, None) == ds.E_INVALID  # n too large
+    assert seg(p._h, fake, None, 1000, offs, 9, 0, ws, None) == ds.E_INVALID  # S too large
+    assert seg(p._h, fake, fake, 1000, offs, 8, 0, ws, None) == ds.E_INVALID  # values, no plan
+    assert seg(p._h, None, None, 1000, offs, 8, 0, ws, None) == ds.E_INVALID
+    assert seg(p._h, fake, None, 1000, None, 8, 0, ws, None) == ds.E_INVALID
+    assert seg(p._h, fake, None, 1000, ctypes.c_void_p(0x30004), 8, 0, ws, None) == ds.E_INVALID
+    assert seg(p._h, fake, None, 1000, offs, 8, 0, ctypes.c_void_p(0x20040), None) == ds.E_INVALID
+    assert seg(None, fake, None, 1000, offs, 8, 0, ws, None) == ds.E_INVALID
+    q = ds.Plan(ds.U32, True, 1000, max_segments=8)
+    assert seg(q._h, fake, None, 1000, offs, 8, 0, ws, None) == ds.E_INVALID  # values missing
+    # empty batch / empty array: no-ops that touch nothing
+    assert seg(p._h, None, None, 0, None, 8, 0, None, None) == ds.OK
+    assert seg(p._h, None, None, 1000, None, 0, 0, None, None) == ds.OK
+    # a plan without segments accepts none
+    r = ds.Plan(ds.U32, False, 1000)
+    assert seg(r._h, fake, None, 1000, offs, 1, 0, ws, None) == ds.E_INVALID

@@ -283,3 +283,32 @@ def test_paper_parameters(oracle_lib):
     assert tr.bucket_size.max() <= p["bucket_bound_2n_over_s"]
     assert (out == np.sort(keys)).all()
     check_trace_invariants(tr, n)
+
+
+# ------------------------------------------------------------------ batches of sorts
+
+def test_segmented_sort_definition(oracle_lib):
+    """A batch of sorts: each segment independently equals numpy's stable sort of that range;
+    gaps between segments, empty and one-item segments are left as they are."""
+    n = 20_000
+    keys = synth.make_u32("bucket", n, 21)
+    vals = synth.index_values(n)
+    offsets = [0, 0, 1, 700, 700, 5000, 5003, 9000, 19_999]  # [9000, 19_999) sorted, tail not
+    k, v = oracle_lib.segmented_sort(keys, offsets, vals)
+    for lo, hi in zip(offsets[:-1], offsets[1:]):
+        order = np.argsort(keys[lo:hi], kind="stable")
+        assert (k[lo:hi] == keys[lo:hi][order]).all()
+        assert (v[lo:hi] == vals[lo:hi][order]).all()
+    assert k[-1] == keys[-1] and v[-1] == vals[-1]
+    # float32 segments under the total order, duplicates and signed zeros included
+    sizes = synth.segment_sizes(6, 4, 2, 11)
+    x = synth.normal_f32_segments(sizes, 4, dup_frac=0.05, zero_log2=4)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    k, _ = oracle_lib.segmented_sort(x, offs)
+    for lo, hi in zip(offs[:-1], offs[1:]):
+        want = sorted(x[lo:hi].view(np.uint32).tolist(), key=_total_order_key)
+        assert k[lo:hi].view(np.uint32).tolist() == want
+    with pytest.raises(ValueError):
+        oracle_lib.segmented_sort(keys, [0, 10, 5])
+    with pytest.raises(ValueError):
+        oracle_lib.segmented_sort(keys, [0, n + 1])
