@@ -6,6 +6,18 @@ timed sort sees the same unsorted input and nothing but sorting happens in the t
 Prints one JSON line with the throughput (Mkeys/s), the per-stage kernel times measured with
 HIP events on the sort's stream over the timed region, the HBM roofline of the dominant kernel,
 and the CPU oracle timed on a bounded sample of the same stream.
+
+A second leg ("batched") times the batched workload -- 4096 independent float32 sorts, sizes
+log-uniform in [2^8, 2^20], N(0,1) keys with 1% exact duplicates and signed zeros -- as one
+segmented call per step, beside the same segments sorted back to back, one plain sort call
+each, on the same stream.
+
+A third leg ("served") runs the served-stream workload: requests of sizes log-uniform in
+[2^10, 2^26], half uint32 keys only and half uint64 keys with uint32 values, keys uniform or
+bucket-clustered, through the library's server (device arena as the memory budget, continuous
+batching of small requests into segmented launches).  It reports throughput when all requests
+are waiting (saturated) and p50/p99 request latency under Poisson arrivals at a stated fraction
+of the back-to-back capacity, beside the same requests sorted back to back with plain calls.
 """
 from __future__ import annotations
 
@@ -96,6 +108,200 @@ def cpu_baseline(seed: int, sample_log2: int, L: int, s: int):
                       f"single-threaded C oracle of Algorithm 1 with L={L}, s={s}; {dt:.1f} s"}
 
 
+def batched_leg(args, ds, torch, dev):
+    """One step = one segmented call over the whole batch; the reference point is the same
+    batch sorted by back-to-back plain calls (one per segment) on the same stream."""
+    import synth
+    S = args.batched_segments
+    sizes = synth.segment_sizes(S, args.batched_seed, 8, 20)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    n = int(offs[-1])
+    log(f"[bench] batched: generating {S} float32 segments, {n} keys (seed {args.batched_seed})")
+    x = synth.normal_f32_segments(sizes, args.batched_seed)
+    src = torch.from_numpy(x.view(np.int32)).to(dev)
+    del x
+    t_off = torch.from_numpy(offs).to(dev)
+    K, W = args.batched_steps, 2
+    bufs = [src.clone() for _ in range(W + K)]
+    max_seg = int(sizes.max())
+    plan = ds.Plan(ds.F32, False, n, max_segments=S)
+    geo = plan.segmented_geometry(n, S, max_seg)
+    ws = plan.workspace(dev)
+    stream = torch.cuda.current_stream(dev)
+    torch.cuda.synchronize()
+    for i in range(W):
+        plan.sort_segmented(bufs[i], t_off, max_segment=max_seg, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    log(f"[bench] batched: timing {K} segmented calls")
+    t0 = time.perf_counter()
+    for i in range(W, W + K):
+        plan.sort_segmented(bufs[i], t_off, max_segment=max_seg, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / K
+    stages = plan.stage_times()
+    plan.set_timing(False)
+    status = int(ws[:4].cpu().numpy().view(np.uint32)[0])
+    assert status == 0, f"kernel status flags {status:#x}"
+    for g in (int(np.argmax(sizes)), int(np.argmin(sizes)), S // 2):
+        seg = bufs[-1][int(offs[g]):int(offs[g + 1])].cpu().numpy().view(np.uint32).astype(
+            np.int64)
+        img = np.where(seg >= 1 << 31, 0xFFFFFFFF - seg, seg + (1 << 31))
+        assert (img[1:] >= img[:-1]).all(), f"segment {g} not sorted"
+    del bufs
+
+    # back to back: one plain call per segment, same stream, same device-resident input
+    pplan = ds.Plan(ds.F32, False, max_seg)
+    pws = pplan.workspace(dev)
+    Kp = args.batched_plain_steps
+    pbufs = [src.clone() for _ in range(1 + Kp)]
+    bounds = [(int(offs[g]), int(offs[g + 1])) for g in range(S)]
+
+    def plain_step(buf):
+        for lo, hi in bounds:
+            pplan.sort_keys(buf[lo:hi], pws, stream)
+
+    plain_step(pbufs[0])
+    torch.cuda.synchronize()
+    log(f"[bench] batched: timing {Kp} back-to-back passes of {S} plain calls")
+    t0 = time.perf_counter()
+    for i in range(1, 1 + Kp):
+        plain_step(pbufs[i])
+    torch.cuda.synchronize()
+    dtp = (time.perf_counter() - t0) / Kp
+    assert torch.equal(pbufs[-1], pbufs[0])
+    del pbufs, src
+    return {
+        "workload": f"{S} independent float32 sorts, sizes log-uniform in [2^8, 2^20] (seed "
+                    f"{args.batched_seed}), N(0,1) keys with 1% duplicates and signed zeros, "
+                    f"IEEE totalOrder, keys only",
+        "n": n, "segments": S, "max_segment": max_seg,
+        "L": geo.sublist_len, "s": geo.samples, "small_capacity": geo.small_capacity,
+        "value": round(n / dt / 1e6, 1), "unit": "Mkeys/s", "steps": K,
+        "ms_per_step": round(dt * 1e3, 4),
+        "back_to_back_mkeys_s": round(n / dtp / 1e6, 1),
+        "back_to_back_ms": round(dtp * 1e3, 3),
+        "speedup_vs_back_to_back": round(dtp / dt, 2),
+        "kernel_ms": {k: round(v[0] * v[1] / K, 4) for k, v in stages.items()},
+    }
+
+
+def served_leg(args, ds, torch, dev):
+    import synth
+    R = args.served_requests
+    sizes = synth.segment_sizes(R, args.served_seed, 10, 26)
+    log(f"[bench] served: generating {R} requests, {int(sizes.sum())} items "
+        f"(seed {args.served_seed})")
+    pristine, work, layouts = [], [], []
+    for i, n in enumerate(sizes.tolist()):
+        dist = "uniform" if (i >> 1) % 2 == 0 else "bucket"
+        if i % 2 == 0:
+            k = synth.make_u32(dist, n, args.served_seed * 7919 + i)
+            pristine.append((torch.from_numpy(k.view(np.int32)).to(dev), None))
+            layouts.append(ds.U32)
+        else:
+            if dist == "uniform":
+                k = synth.uniform_u64(n, args.served_seed * 7919 + i)
+            else:  # bucket-clustered: 64 groups over the 64-bit range
+                u = synth.uniform_u64(n, args.served_seed * 7919 + i)
+                grp = (np.arange(n, dtype=np.uint64) * np.uint64(64)) // np.uint64(max(n, 1))
+                k = (grp << np.uint64(58)) | (u >> np.uint64(6))
+            v = synth.index_values(n)
+            pristine.append((torch.from_numpy(k.view(np.int64)).to(dev),
+                             torch.from_numpy(v.view(np.int32)).to(dev)))
+            layouts.append(ds.U64)
+    for kk, vv in pristine:
+        work.append((torch.empty_like(kk), None if vv is None else torch.empty_like(vv)))
+    total = int(sizes.sum())
+
+    def reset():
+        for (pk, pv), (wk, wv) in zip(pristine, work):
+            wk.copy_(pk)
+            if pv is not None:
+                wv.copy_(pv)
+        torch.cuda.synchronize()
+
+    # back to back: one plain call per request, in arrival order, one stream
+    stream = torch.cuda.current_stream(dev)
+    plans = {ds.U32: ds.Plan(ds.U32, False, int(sizes.max())),
+             ds.U64: ds.Plan(ds.U64, True, int(sizes.max()))}
+    wss = {kt: p.workspace(dev) for kt, p in plans.items()}
+
+    def b2b():
+        for (wk, wv), kt in zip(work, layouts):
+            if wv is None:
+                plans[kt].sort_keys(wk, wss[kt], stream)
+            else:
+                plans[kt].sort_pairs(wk, wv, wss[kt], stream)
+
+    reset()
+    b2b()
+    torch.cuda.synchronize()
+    reset()
+    t0 = time.perf_counter()
+    b2b()
+    torch.cuda.synchronize()
+    t_b2b = time.perf_counter() - t0
+    ref = [(wk.clone(), None if wv is None else wv.clone()) for wk, wv in work]
+    del wss, plans
+
+    srv = ds.Server(args.served_budget_gb << 30, max_inflight=args.served_inflight,
+                    lanes=args.served_lanes)
+
+    def run(gaps):
+        reset()
+        tickets = []
+        t_start = time.perf_counter()
+        t_next = t_start
+        for (wk, wv), kt, gap in zip(work, layouts, gaps):
+            t_next += gap
+            while time.perf_counter() < t_next:
+                pass
+            tickets.append(srv.submit(wk, wv, key_type=kt, sync=False))
+        res = [srv.wait(t, timeout_s=300) for t in tickets]
+        span = (max(r.t_done_ns for r in res) - min(r.t_submit_ns for r in res)) * 1e-9
+        lat = np.array([r.latency_s for r in res])
+        for t in tickets:
+            srv.release(t)
+        return span, lat
+
+    run(np.zeros(R))  # warm-up
+    log("[bench] served: saturated run")
+    span_sat, lat_sat = run(np.zeros(R))
+    for (wk, wv), (rk, rv) in zip(work, ref):
+        assert torch.equal(wk, rk) and (wv is None or torch.equal(wv, rv)), "served != plain"
+    rate = args.served_load * R / t_b2b  # requests per second
+    u = (synth.draws64(args.served_seed + 1, R) >> np.uint64(11)).astype(np.float64) / 2.0**53
+    gaps = -np.log(1.0 - u) / rate
+    log(f"[bench] served: Poisson run at {args.served_load:.2f} x back-to-back capacity")
+    span_p, lat_p = run(gaps)
+    for (wk, wv), (rk, rv) in zip(work, ref):
+        assert torch.equal(wk, rk) and (wv is None or torch.equal(wv, rv)), "served != plain"
+    st = srv.stats()
+    srv.close()
+    del pristine, work, ref
+    return {
+        "workload": f"{R} requests, sizes log-uniform in [2^10, 2^26] (seed {args.served_seed}), "
+                    f"alternating uint32 keys-only and uint64-key/uint32-value pairs, uniform or "
+                    f"bucket-clustered keys; device arena {args.served_budget_gb} GiB, "
+                    f"{args.served_lanes} lanes",
+        "items": total,
+        "back_to_back_mkeys_s": round(total / t_b2b / 1e6, 1),
+        "back_to_back_ms": round(t_b2b * 1e3, 3),
+        "saturated_mkeys_s": round(total / span_sat / 1e6, 1),
+        "saturated_speedup_vs_back_to_back": round(t_b2b / span_sat, 3),
+        "saturated_p50_ms": round(float(np.percentile(lat_sat, 50)) * 1e3, 3),
+        "saturated_p99_ms": round(float(np.percentile(lat_sat, 99)) * 1e3, 3),
+        "offered_load": args.served_load,
+        "poisson_mkeys_s": round(total / span_p / 1e6, 1),
+        "poisson_p50_ms": round(float(np.percentile(lat_p, 50)) * 1e3, 3),
+        "poisson_p99_ms": round(float(np.percentile(lat_p, 99)) * 1e3, 3),
+        "units": st["units"], "batched_units": st["batched_units"],
+        "batched_requests": st["batched_requests"], "max_batch": st["max_batch"],
+        "peak_arena_gib": round(st["peak_arena_bytes"] / 2**30, 3),
+    }
+
+
 def _group_of(kernel: str, seen: dict) -> str:
     """Maps a rocprofv3 kernel name of one sort to its stage group; the Step 1-3 tile kernels
     run once per level, so their first launch in a sort is level 1 and the second level 2."""
@@ -180,6 +386,18 @@ def main():
                     help="turn two rocprofv3 counter CSVs of a --copy-calibration run into "
                          "profiles/traffic.json (CPU only)")
     ap.add_argument("--sorts", type=int, default=1, help="sorts in the ingested runs")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
+    ap.add_argument("--batched-segments", type=int, default=4096)
+    ap.add_argument("--batched-seed", type=int, default=4)
+    ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--batched-plain-steps", type=int, default=2)
+    ap.add_argument("--no-served", action="store_true", help="skip the served leg")
+    ap.add_argument("--served-requests", type=int, default=128)
+    ap.add_argument("--served-seed", type=int, default=12)
+    ap.add_argument("--served-load", type=float, default=0.7)
+    ap.add_argument("--served-budget-gb", type=int, default=64)
+    ap.add_argument("--served-lanes", type=int, default=4)
+    ap.add_argument("--served-inflight", type=int, default=1024)
     args = ap.parse_args()
     if args.ingest_pmc:
         ingest_pmc(args.ingest_pmc[0], args.ingest_pmc[1], args.copy_calibration, args.sorts,
@@ -259,6 +477,13 @@ def main():
                     "algorithmic_bytes": alg, "ms_per_step": round(t_ms, 4),
                     "launches_per_step": sum(stages[nm][1] for nm in STAGE_GROUPS[dom]
                                              if nm in stages) // K}
+    del bufs
+    batched = None
+    if not args.no_batched:
+        batched = batched_leg(args, ds, torch, dev)
+    served = None
+    if not args.no_served:
+        served = served_leg(args, ds, torch, dev)
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -288,6 +513,8 @@ def main():
         "kernel_ms": stage_ms,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "served": served,
     }
     print(json.dumps(rec), flush=True)
 

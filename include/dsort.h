@@ -171,6 +171,65 @@ typedef struct {
 int dsort_segmented_geometry(dsort_plan_t plan, uint64_t n, uint64_t num_segments,
                              uint64_t max_segment, dsort_seg_geometry_t *out);
 
+/* ------------------------------------------------------------------------ served stream
+ * A server sorts a stream of independent requests, each an array already in device memory
+ * (caller-owned, sorted in place), as they arrive.  It owns a device arena of
+ * `hbm_budget_bytes` (allocated at creation) from which every launch takes its workspace, and
+ * `lanes` HIP streams (default priority) on which up to `lanes` launches overlap.  A background
+ * thread forms the launches: when a lane is free it takes the oldest waiting request; requests
+ * no longer than dsort_segmented's segment limit for their key layout are batched with the other
+ * waiting ones of the same layout (key type and values or not) into one segmented sort (their
+ * items are copied to a staging block of the arena and back); longer requests run alone as
+ * dsort_keys/dsort_pairs would, in place.  A launch starts only if its memory fits the arena,
+ * else the oldest request waits (first come, first served), and at most `max_inflight`
+ * requests run at once.  Results are exactly those of dsort_keys/dsort_pairs on each request
+ * alone.  The request's data must be complete in device memory when it is submitted (the
+ * server's streams do not wait for other streams), and its buffers must stay valid and untouched
+ * until dsort_poll reports it finished; two requests must not share memory. */
+typedef struct dsort_server_s *dsort_server_t;
+
+typedef struct {
+    int key_type;        /* DSORT_U32 / DSORT_U64 / DSORT_F32 */
+    int with_values;     /* 1: d_values holds n uint32 values (stable key/value sort) */
+    void *d_keys;        /* n keys, device memory, natural alignment */
+    uint32_t *d_values;  /* n values or NULL */
+    uint64_t n;
+} dsort_request_t;
+
+typedef struct {
+    int state;           /* 0 waiting, 1 running, 2 done, negative: failed with that status */
+    int reserved;
+    uint64_t t_submit_ns, t_admit_ns, t_done_ns;  /* steady clock; 0 = not reached */
+    uint64_t unit;       /* launch that ran it (requests of one batch share it) */
+} dsort_result_t;
+
+typedef struct {
+    uint64_t submitted, completed, failed;
+    uint64_t units;              /* launches */
+    uint64_t batched_units;      /* launches that sorted more than one request */
+    uint64_t batched_requests;   /* requests sorted inside such launches */
+    uint64_t max_batch;          /* most requests in one launch */
+    uint64_t peak_arena_bytes;   /* most arena bytes in use at once */
+    uint64_t peak_running_units; /* most launches on the device at once */
+} dsort_server_stats_t;
+
+/* Creates a server on the calling thread's current device.  lanes in 1..16; max_inflight >= 1
+ * (also the most requests one batch holds, at most 4096).  Errors: DSORT_E_INVALID (budget
+ * under 1 MiB, bad counts), DSORT_E_NOMEM (the arena could not be allocated), DSORT_E_HIP. */
+int dsort_server_create(dsort_server_t *out, uint64_t hbm_budget_bytes, uint32_t max_inflight,
+                        uint32_t lanes);
+/* Queues a request and returns at once with its ticket.  Errors: DSORT_E_INVALID (bad type,
+ * pointers or alignment), DSORT_E_CAPACITY (the request alone needs more memory than the arena
+ * holds, or has no feasible plan). */
+int dsort_submit(dsort_server_t server, const dsort_request_t *req, uint64_t *ticket);
+/* Current state and timestamps of a ticket (never blocks).  DSORT_E_TICKET if unknown. */
+int dsort_poll(dsort_server_t server, uint64_t ticket, dsort_result_t *out);
+/* Forgets a finished ticket.  DSORT_E_INVALID if it is still waiting or running. */
+int dsort_release(dsort_server_t server, uint64_t ticket);
+int dsort_server_stats(dsort_server_t server, dsort_server_stats_t *out);
+/* Waits for every queued and running request, then frees the server (NULL is accepted). */
+int dsort_server_destroy(dsort_server_t server);
+
 /* Per-kernel timing, for profiling.  dsort_set_timing(plan, 1) clears the record and makes
  * every later sorting call on `plan` bracket each kernel launch with two HIP events recorded
  * on the call's stream (events are created on first use and owned by the plan); 0 stops

@@ -13,7 +13,7 @@ from dataclasses import dataclass
 
 __all__ = [
     "U32", "U64", "F32", "DsortError", "Tuning", "Plan", "load_library", "sort", "sort_pairs",
-    "sort_segmented", "strerror", "EXPORTED_SYMBOLS",
+    "sort_segmented", "Server", "strerror", "EXPORTED_SYMBOLS",
 ]
 
 U32, U64, F32 = 1, 2, 3
@@ -26,6 +26,8 @@ EXPORTED_SYMBOLS = (
     "dsort_plan", "dsort_keys", "dsort_pairs", "dsort_plan_destroy", "dsort_strerror",
     "dsort_plan_geometry", "dsort_set_timing", "dsort_stage_times", "dsort_last_error",
     "dsort_segmented", "dsort_segmented_geometry",
+    "dsort_server_create", "dsort_submit", "dsort_poll", "dsort_release", "dsort_server_stats",
+    "dsort_server_destroy",
 )
 
 
@@ -65,6 +67,24 @@ class _SegGeometry(ctypes.Structure):
                 ("max_sublists", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("bucket_bound", ctypes.c_uint64), ("off_status", ctypes.c_uint64),
                 ("workspace_bytes", ctypes.c_uint64)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("key_type", ctypes.c_int), ("with_values", ctypes.c_int),
+                ("d_keys", ctypes.c_void_p), ("d_values", ctypes.c_void_p),
+                ("n", ctypes.c_uint64)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64), ("unit", ctypes.c_uint64)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in (
+        "submitted", "completed", "failed", "units", "batched_units", "batched_requests",
+        "max_batch", "peak_arena_bytes", "peak_running_units")]
 
 
 _lib = None
@@ -110,6 +130,19 @@ def load_library(path: str = LIB_PATH):
     lib.dsort_segmented.restype = I
     lib.dsort_segmented_geometry.argtypes = [P, U64_, U64_, U64_, ctypes.POINTER(_SegGeometry)]
     lib.dsort_segmented_geometry.restype = I
+    lib.dsort_server_create.argtypes = [ctypes.POINTER(P), U64_, ctypes.c_uint32,
+                                        ctypes.c_uint32]
+    lib.dsort_server_create.restype = I
+    lib.dsort_submit.argtypes = [P, ctypes.POINTER(_Request), ctypes.POINTER(U64_)]
+    lib.dsort_submit.restype = I
+    lib.dsort_poll.argtypes = [P, U64_, ctypes.POINTER(_Result)]
+    lib.dsort_poll.restype = I
+    lib.dsort_release.argtypes = [P, U64_]
+    lib.dsort_release.restype = I
+    lib.dsort_server_stats.argtypes = [P, ctypes.POINTER(_ServerStats)]
+    lib.dsort_server_stats.restype = I
+    lib.dsort_server_destroy.argtypes = [P]
+    lib.dsort_server_destroy.restype = I
     lib.dsort_last_error.argtypes = []
     lib.dsort_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -350,3 +383,92 @@ def sort_segmented(keys, offsets, values=None, key_type: int | None = None, max_
     if k not in _plans:
         _plans[k] = Plan(kt, values is not None, cap, max_segments=scap)
     return _plans[k].sort_segmented(keys, offsets, values, max_segment=max_segment, stream=stream)
+
+
+QUEUED, RUNNING, DONE = 0, 1, 2
+
+
+@dataclass
+class Result:
+    state: int
+    t_submit_ns: int
+    t_admit_ns: int
+    t_done_ns: int
+    unit: int
+
+    @property
+    def latency_s(self) -> float:
+        return (self.t_done_ns - self.t_submit_ns) * 1e-9
+
+
+class Server:
+    """A served sort stream (native scheduler thread, device arena of ``budget_bytes``, ``lanes``
+    HIP streams).  ``submit`` queues an in-place sort of device tensors and returns a ticket;
+    the tensors are kept referenced here until the ticket is released."""
+
+    def __init__(self, budget_bytes: int, max_inflight: int = 1024, lanes: int = 4):
+        import torch  # noqa: F401  (device and runtime come from torch)
+        lib = load_library()
+        self._lib = lib
+        h = ctypes.c_void_p()
+        _check(lib.dsort_server_create(ctypes.byref(h), int(budget_bytes), int(max_inflight),
+                                       int(lanes)), "dsort_server_create")
+        self._h = h
+        self._held = {}
+
+    def submit(self, keys, values=None, key_type: int | None = None, sync: bool = True) -> int:
+        """Queues an in-place sort.  The server's streams do not wait for other streams, so by
+        default the current stream (which produced the data) is synchronised first."""
+        kt = _key_type_of(keys, key_type)
+        if sync:
+            import torch
+            torch.cuda.current_stream(keys.device).synchronize()
+        ksz = 8 if kt == U64 else 4
+        kp = Plan._dev_ptr(keys, ksz, "keys")
+        vp = None
+        if values is not None:
+            if values.numel() != keys.numel():
+                raise ValueError("keys and values differ in length")
+            vp = Plan._dev_ptr(values, 4, "values")
+        r = _Request(kt, int(values is not None), kp, vp, keys.numel())
+        t = ctypes.c_uint64()
+        _check(self._lib.dsort_submit(self._h, ctypes.byref(r), ctypes.byref(t)), "dsort_submit")
+        self._held[t.value] = (keys, values)
+        return t.value
+
+    def poll(self, ticket: int) -> Result:
+        r = _Result()
+        _check(self._lib.dsort_poll(self._h, int(ticket), ctypes.byref(r)), "dsort_poll")
+        return Result(r.state, r.t_submit_ns, r.t_admit_ns, r.t_done_ns, r.unit)
+
+    def wait(self, ticket: int, timeout_s: float = 60.0, sleep_s: float = 2e-5) -> Result:
+        import time
+        t0 = time.monotonic()
+        while True:
+            r = self.poll(ticket)
+            if r.state == DONE or r.state < 0:
+                if r.state < 0:
+                    raise DsortError(r.state, f"request {ticket}")
+                return r
+            if time.monotonic() - t0 > timeout_s:
+                raise TimeoutError(f"request {ticket} not finished after {timeout_s} s")
+            time.sleep(sleep_s)
+
+    def release(self, ticket: int):
+        _check(self._lib.dsort_release(self._h, int(ticket)), "dsort_release")
+        self._held.pop(ticket, None)
+
+    def stats(self) -> dict:
+        s = _ServerStats()
+        _check(self._lib.dsort_server_stats(self._h, ctypes.byref(s)), "dsort_server_stats")
+        return {f: int(getattr(s, f)) for f, _ in _ServerStats._fields_}
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.dsort_server_destroy(h)
+            self._h = None
+            self._held.clear()
+
+    def __del__(self):
+        self.close()

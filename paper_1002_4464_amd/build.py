@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdsort.so")
-SOURCES = ["kernels.hip", "plan.cpp"]
+SOURCES = ["kernels.hip", "plan.cpp", "server.cpp"]
 ARCH = "gfx950"
 
 
@@ -25,12 +25,16 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the dsort library needs ROCm's hipcc to build")
 
 
+def rocm_include() -> str:
+    return os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(hipcc()))), "include")
+
+
 def build(verbose: bool = False) -> str:
     """Compiles every source and links libdsort.so; always rebuilds."""
     out_dir = os.path.join(HERE, "_build")
     os.makedirs(out_dir, exist_ok=True)
     objs = []
-    common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include")]
+    common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-pthread", "-I", os.path.join(ROOT, "include")]
     for src in SOURCES:
         obj = os.path.join(out_dir, src + ".o")
         cmd = [hipcc(), *common, "-c", os.path.join(CSRC, src), "-o", obj]
@@ -38,13 +42,13 @@ def build(verbose: bool = False) -> str:
             cmd[1:1] = [f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
                         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
         else:
-            cmd[1:1] = ["-x", "c++"]
+            cmd[1:1] = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", rocm_include()]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = [hipcc(), "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

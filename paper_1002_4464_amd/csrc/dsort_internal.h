@@ -107,6 +107,10 @@ int make_seg_geom(int key_type, bool values, uint64_t n, uint64_t S, uint64_t ma
                   SegGeom &g);
 int run_segmented(const SegGeom &g, void *d_keys, uint32_t *d_vals, const uint64_t *d_off,
                   void *d_ws, void *stream, Timing *tm);
+// Copies between requests' own buffers and a staging array (served-stream batches).
+int launch_pack(int key_bytes, const uint64_t *d_src_keys, const uint64_t *d_src_vals,
+                const uint64_t *d_off, uint32_t S, uint64_t total, void *stage_keys,
+                uint32_t *stage_vals, bool unpack, void *stream);
 int run_pipeline(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, void *stream,
                  Timing *tm);
 

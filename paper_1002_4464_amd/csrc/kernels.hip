@@ -1853,6 +1853,65 @@ int timing_summary(Timing &t, const char **names, float *avg_ms, uint32_t *launc
     return DSORT_OK;
 }
 
+// Batch staging for the served stream: copies request g's items between its own buffers
+// (keys at src_keys[g], values at src_vals[g]) and positions [off[g], off[g+1]) of one staging
+// array, in either direction.  Each workgroup moves one chunk of kPackChunk staging positions,
+// finding the request of its first position by bisection and walking forward from there.
+constexpr uint32_t kPackChunk = 8192;
+
+template <class K>
+__global__ __launch_bounds__(256) void k_pack(const uint64_t *src_keys, const uint64_t *src_vals,
+                                              const uint64_t *off, uint32_t S, K *stage_keys,
+                                              uint32_t *stage_vals, uint32_t unpack) {
+    const uint64_t total = off[S];
+    const uint64_t c0 = (uint64_t)blockIdx.x * kPackChunk;
+    if (c0 >= total) return;
+    const uint64_t c1 = min(total, c0 + kPackChunk);
+    uint32_t lo = 0, hi = S - 1;  // last g with off[g] <= c0
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= c0) lo = mid; else hi = mid - 1;
+    }
+    for (uint32_t g = lo; g < S && off[g] < c1; ++g) {
+        const uint64_t a = max(off[g], c0), b = min(off[g + 1], c1);
+        K *uk = (K *)src_keys[g];
+        uint32_t *uv = (uint32_t *)src_vals[g];
+        for (uint64_t x = a + threadIdx.x; x < b; x += blockDim.x) {
+            const uint64_t r = x - off[g];
+            if (unpack) {
+                uk[r] = stage_keys[x];
+                if (stage_vals) uv[r] = stage_vals[x];
+            } else {
+                stage_keys[x] = uk[r];
+                if (stage_vals) stage_vals[x] = uv[r];
+            }
+        }
+    }
+}
+
+int launch_pack(int key_bytes, const uint64_t *d_src_keys, const uint64_t *d_src_vals,
+                const uint64_t *d_off, uint32_t S, uint64_t total, void *stage_keys,
+                uint32_t *stage_vals, bool unpack, void *stream) {
+    if (S == 0 || total == 0) return DSORT_OK;
+    const uint64_t chunks = (total + kPackChunk - 1) / kPackChunk;
+    if (chunks > 0x7FFFFFFFu) return DSORT_E_CAPACITY;
+    hipStream_t st = (hipStream_t)stream;
+    if (key_bytes == 8)
+        hipLaunchKernelGGL((k_pack<uint64_t>), dim3((uint32_t)chunks), dim3(256), 0, st,
+                           d_src_keys, d_src_vals, d_off, S, (uint64_t *)stage_keys, stage_vals,
+                           unpack ? 1u : 0u);
+    else
+        hipLaunchKernelGGL((k_pack<uint32_t>), dim3((uint32_t)chunks), dim3(256), 0, st,
+                           d_src_keys, d_src_vals, d_off, S, (uint32_t *)stage_keys, stage_vals,
+                           unpack ? 1u : 0u);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_last_error(unpack ? "unpack" : "pack", hipGetErrorName(e), hipGetErrorString(e));
+        return DSORT_E_HIP;
+    }
+    return DSORT_OK;
+}
+
 int run_segmented(const SegGeom &g, void *d_keys, uint32_t *d_vals, const uint64_t *d_off,
                   void *d_ws, void *stream, Timing *tm) {
     hipStream_t st = (hipStream_t)stream;

@@ -171,3 +171,22 @@ def test_segmented_rejects_bad_arguments_without_gpu():
     # a plan without segments accepts none
     r = ds.Plan(ds.U32, False, 1000)
     assert seg(r._h, fake, None, 1000, offs, 1, 0, ws, None) == ds.E_INVALID
+
+
+def test_server_rejects_bad_arguments_without_gpu():
+    lib = ds.load_library()
+    h = ctypes.c_void_p()
+    assert lib.dsort_server_create(None, 1 << 30, 16, 2) == ds.E_INVALID
+    assert lib.dsort_server_create(ctypes.byref(h), 1000, 16, 2) == ds.E_INVALID  # < 1 MiB
+    assert lib.dsort_server_create(ctypes.byref(h), 1 << 30, 0, 2) == ds.E_INVALID
+    assert lib.dsort_server_create(ctypes.byref(h), 1 << 30, 16, 0) == ds.E_INVALID
+    assert lib.dsort_server_create(ctypes.byref(h), 1 << 30, 16, 17) == ds.E_INVALID
+    t = ctypes.c_uint64()
+    r = ds._Request(1, 0, None, None, 10)
+    assert lib.dsort_submit(None, ctypes.byref(r), ctypes.byref(t)) == ds.E_INVALID
+    res = ds._Result()
+    assert lib.dsort_poll(None, 1, ctypes.byref(res)) == ds.E_INVALID
+    assert lib.dsort_release(None, 1) == ds.E_INVALID
+    st = ds._ServerStats()
+    assert lib.dsort_server_stats(None, ctypes.byref(st)) == ds.E_INVALID
+    assert lib.dsort_server_destroy(None) == ds.OK
