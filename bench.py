@@ -392,6 +392,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--batched-plain-steps", type=int, default=2)
     ap.add_argument("--no-served", action="store_true", help="skip the served leg")
+    ap.add_argument("--only", choices=["batched", "served"],
+                    help="run only that leg and print its record (for profiling)")
     ap.add_argument("--served-requests", type=int, default=128)
     ap.add_argument("--served-seed", type=int, default=12)
     ap.add_argument("--served-load", type=float, default=0.7)
@@ -415,6 +417,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.only:
+        leg = batched_leg if args.only == "batched" else served_leg
+        print(json.dumps({args.only: leg(args, ds, torch, dev)}), flush=True)
+        return
     n = 1 << args.log2n
     K, W = args.steps, args.warmup
 
