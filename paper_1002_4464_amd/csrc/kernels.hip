@@ -48,6 +48,19 @@ __device__ __forceinline__ bool lt(const C128 &a, const C128 &b) {
     return a.key < b.key || (a.key == b.key && a.pos < b.pos);
 }
 
+// c ? a : b, field by field for the composite (a whole-struct select is lowered through
+// scratch memory).
+template <class T> __device__ __forceinline__ T sel(bool c, const T &a, const T &b) {
+    return c ? a : b;
+}
+template <> __device__ __forceinline__ C128 sel<C128>(bool c, const C128 &a, const C128 &b) {
+    C128 r;
+    r.key = c ? a.key : b.key;
+    r.pos = c ? a.pos : b.pos;
+    r.unused = 0u;
+    return r;
+}
+
 template <class T> struct MaxOf;
 template <> struct MaxOf<uint32_t> {
     static __device__ __forceinline__ uint32_t get() { return 0xFFFFFFFFu; }
@@ -180,8 +193,8 @@ __device__ __forceinline__ uint32_t pow2_at_least(uint32_t x) {
 
 template <class T> __device__ __forceinline__ void cmpx(T &a, T &b) {
     const bool sw = lt(b, a);
-    const T lo = sw ? b : a;
-    const T hi = sw ? a : b;
+    const T lo = sel(sw, b, a);
+    const T hi = sel(sw, a, b);
     a = lo;
     b = hi;
 }
@@ -249,12 +262,12 @@ __device__ __forceinline__ void serial_merge_nc(const T *lds, uint32_t ai, uint3
 #pragma unroll
     for (int k = 0; k < E; ++k) {
         const bool take_a = (bi >= b_end) || ((ai < a_end) && !lt(bv, av));
-        out[k] = take_a ? av : bv;
+        out[k] = sel(take_a, av, bv);
         ai += take_a ? 1u : 0u;
         bi += take_a ? 0u : 1u;
         const T v = lds_at<T>(lds, take_a ? ai : bi);
-        av = take_a ? v : av;
-        bv = take_a ? bv : v;
+        av = sel(take_a, v, av);
+        bv = sel(take_a, bv, v);
     }
 }
 
@@ -269,13 +282,13 @@ __device__ __forceinline__ void serial_merge(const T *lds, uint32_t ai, uint32_t
 #pragma unroll
     for (int k = 0; k < E; ++k) {
         const bool take_a = (bi >= b_end) || ((ai < a_end) && !lt(bv, av));
-        out[k] = take_a ? av : bv;
+        out[k] = sel(take_a, av, bv);
         const uint32_t nxt = take_a ? ai + 1 : bi + 1;
         ai = take_a ? ai + 1 : ai;
         bi = take_a ? bi : bi + 1;
         const T v = lds[pidx<T>(min(nxt, lim))];
-        av = take_a ? v : av;
-        bv = take_a ? bv : v;
+        av = sel(take_a, v, av);
+        bv = sel(take_a, bv, v);
     }
 }
 
