@@ -48,6 +48,26 @@ __device__ __forceinline__ bool lt(const C128 &a, const C128 &b) {
     return a.key < b.key || (a.key == b.key && a.pos < b.pos);
 }
 
+// Order used by the merge passes.  COMP: the elements are (key, position) composites whose
+// positions increase with their initial LDS (or array) index, so inside a merge of two adjacent
+// runs every position of the earlier run is below every position of the later one, and the
+// composite order is the key order with ties going to the earlier run.  The merges take the
+// earlier run on ties, so comparing keys alone gives the composite order.
+template <class T, bool COMP> struct MergeLess {
+    static __device__ __forceinline__ bool f(const T &a, const T &b) { return lt(a, b); }
+};
+template <> struct MergeLess<uint64_t, true> {  // (key << 32) | position
+    static __device__ __forceinline__ bool f(uint64_t a, uint64_t b) {
+        return (uint32_t)(a >> 32) < (uint32_t)(b >> 32);
+    }
+};
+template <> struct MergeLess<C128, true> {
+    static __device__ __forceinline__ bool f(const C128 &a, const C128 &b) { return a.key < b.key; }
+};
+template <bool COMP, class T> __device__ __forceinline__ bool mlt(const T &a, const T &b) {
+    return MergeLess<T, COMP>::f(a, b);
+}
+
 // c ? a : b, field by field for the composite (a whole-struct select is lowered through
 // scratch memory).
 template <class T> __device__ __forceinline__ T sel(bool c, const T &a, const T &b) {
@@ -238,7 +258,7 @@ template <class T> __device__ __forceinline__ T lds_at(const T *lds, uint32_t i)
 
 // Merge path: number of A items among the first `diag` outputs of the stable merge of
 // A = lds[a0, a0+na) and B = lds[b0, b0+nb) (A wins ties).
-template <class T>
+template <class T, bool COMP = false>
 __device__ __forceinline__ uint32_t merge_path(const T *lds, uint32_t a0, uint32_t na,
                                                uint32_t b0, uint32_t nb, uint32_t diag) {
     uint32_t lo = diag > nb ? diag - nb : 0;
@@ -247,21 +267,21 @@ __device__ __forceinline__ uint32_t merge_path(const T *lds, uint32_t a0, uint32
         const uint32_t mid = (lo + hi) >> 1;
         const T av = lds_at<T>(lds, a0 + mid);
         const T bv = lds_at<T>(lds, b0 + diag - 1 - mid);
-        if (lt(bv, av)) hi = mid; else lo = mid + 1;
+        if (mlt<COMP>(bv, av)) hi = mid; else lo = mid + 1;
     }
     return lo;
 }
 
 // Serial stable merge of E outputs starting at A index ai (< a_end) / B index bi (< b_end),
 // for an LDS array with one readable element past every index it can reach (so no clamp).
-template <class T, int E>
+template <class T, int E, bool COMP = false>
 __device__ __forceinline__ void serial_merge_nc(const T *lds, uint32_t ai, uint32_t a_end,
                                                 uint32_t bi, uint32_t b_end, T (&out)[E]) {
     T av = lds_at<T>(lds, ai);
     T bv = lds_at<T>(lds, bi);
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-        const bool take_a = (bi >= b_end) || ((ai < a_end) && !lt(bv, av));
+        const bool take_a = (bi >= b_end) || ((ai < a_end) && !mlt<COMP>(bv, av));
         out[k] = sel(take_a, av, bv);
         ai += take_a ? 1u : 0u;
         bi += take_a ? 0u : 1u;
@@ -273,7 +293,7 @@ __device__ __forceinline__ void serial_merge_nc(const T *lds, uint32_t ai, uint3
 
 // Serial stable merge of E outputs starting at A index ai (< a_end) / B index bi (< b_end).
 // `lim` is any valid LDS index used to keep speculative reads in bounds.
-template <class T, int E>
+template <class T, int E, bool COMP = false>
 __device__ __forceinline__ void serial_merge(const T *lds, uint32_t ai, uint32_t a_end,
                                              uint32_t bi, uint32_t b_end, uint32_t lim,
                                              T (&out)[E]) {
@@ -281,7 +301,7 @@ __device__ __forceinline__ void serial_merge(const T *lds, uint32_t ai, uint32_t
     T bv = lds[pidx<T>(min(bi, lim))];
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-        const bool take_a = (bi >= b_end) || ((ai < a_end) && !lt(bv, av));
+        const bool take_a = (bi >= b_end) || ((ai < a_end) && !mlt<COMP>(bv, av));
         out[k] = sel(take_a, av, bv);
         const uint32_t nxt = take_a ? ai + 1 : bi + 1;
         ai = take_a ? ai + 1 : ai;
@@ -296,8 +316,10 @@ __device__ __forceinline__ void serial_merge(const T *lds, uint32_t ai, uint32_t
 // lds_elems(P) + 1 elements, the last one only ever read speculatively).  Thread t owns
 // items [tE, tE+E): a register network sorts them, then merge passes double the sorted run
 // length; when P is not a power of two the last run of a pass is shorter (or has no partner).
-// All threads of the block must call it.
-template <class T, int E> __device__ __forceinline__ void block_sort(T *lds, uint32_t P) {
+// All threads of the block must call it.  COMP: see MergeLess (the register network always
+// compares whole elements; only the merges may compare keys alone).
+template <class T, int E, bool COMP = false>
+__device__ __forceinline__ void block_sort(T *lds, uint32_t P) {
     const uint32_t t = threadIdx.x;
     const bool act = t * E < P;
     T x[E];
@@ -316,9 +338,9 @@ template <class T, int E> __device__ __forceinline__ void block_sort(T *lds, uin
             const uint32_t diag = start - base;
             const uint32_t na = min(R, P - base);
             const uint32_t nb = min(R, P - base - na);
-            const uint32_t a = merge_path<T>(lds, base, na, base + na, nb, diag);
-            serial_merge_nc<T, E>(lds, base + a, base + na, base + na + diag - a, base + na + nb,
-                                  x);
+            const uint32_t a = merge_path<T, COMP>(lds, base, na, base + na, nb, diag);
+            serial_merge_nc<T, E, COMP>(lds, base + a, base + na, base + na + diag - a,
+                                        base + na + nb, x);
         }
         __syncthreads();
         if (act) {
@@ -604,7 +626,7 @@ __global__ __launch_bounds__(CAP / E) void k_tile(TileArgs a) {
         lds[pidx<T>(i)] = e;
     }
     __syncthreads();
-    block_sort<T, E>(lds, P);
+    block_sort<T, E, V>(lds, P);  // key/value elements carry their load position
 
     if (MODE == MODE_SAMPLE) {
         typename R::SC *smp = (typename R::SC *)a.samples;
@@ -677,7 +699,7 @@ __global__ __launch_bounds__(CAP / E) void k_sort_samples(const SC *src, SC *dst
     for (uint32_t i = tid; i < P; i += blockDim.x)
         lds[pidx<SC>(i)] = i < count ? src[begin + i] : MaxOf<SC>::get();
     __syncthreads();
-    block_sort<SC, E>(lds, P);
+    block_sort<SC, E, true>(lds, P);  // sample composites are in position order
     for (uint32_t i = tid; i < count; i += blockDim.x) dst[begin + i] = lds[pidx<SC>(i)];
 }
 
@@ -701,7 +723,7 @@ __global__ __launch_bounds__(CAP / E) void k_merge_round(const SC *src, SC *dst,
         uint32_t lo = d > nb ? d - nb : 0, hi = min(d, na);
         while (lo < hi) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (lt(src[b0 + d - 1 - mid], src[a0 + mid])) hi = mid; else lo = mid + 1;
+            if (mlt<true>(src[b0 + d - 1 - mid], src[a0 + mid])) hi = mid; else lo = mid + 1;
         }
         split[tid] = lo;
     }
@@ -714,9 +736,9 @@ __global__ __launch_bounds__(CAP / E) void k_merge_round(const SC *src, SC *dst,
     const uint32_t diag = tid * E;
     const uint32_t tot = la + lb;
     if (diag < tot) {
-        const uint32_t x = merge_path<SC>(lds, 0, la, la, lb, diag);
+        const uint32_t x = merge_path<SC, true>(lds, 0, la, la, lb, diag);
         SC out[E];
-        serial_merge<SC, E>(lds, x, la, la + diag - x, tot, tot - 1, out);
+        serial_merge<SC, E, true>(lds, x, la, la + diag - x, tot, tot - 1, out);
 #pragma unroll
         for (int k = 0; k < E; ++k)
             if (diag + k < tot) dst[c0 + diag + k] = out[k];
@@ -1112,9 +1134,18 @@ constexpr uint32_t kMaxPieces = 256;
 
 // Items per thread of the merge-sort bucket kernel: 16 (8 for 16-byte elements), raised so that
 // CAP / E <= 1024 threads.
+#ifndef DSORT_PAIR_GATHER_E
+#define DSORT_PAIR_GATHER_E 8  // items per thread of the key/value bucket sorts
+#endif
+#ifndef DSORT_PAIR_GATHER_WPE
+#define DSORT_PAIR_GATHER_WPE 4  // minimum waves per SIMD asked of the key/value bucket sorts
+#endif
 template <class K, bool V, int CAP> struct GatherE {
-    static constexpr int base = sizeof(typename Tr<K, V>::T) >= 16 ? 8 : 16;
-    static constexpr int E = CAP / base > 1024 ? CAP / 1024 : base;
+    static constexpr int base =
+        sizeof(typename Tr<K, V>::T) >= 16 ? 8 : (V ? DSORT_PAIR_GATHER_E : 16);
+    static constexpr int E = CAP / base > 1024 ? (CAP / 1024 <= 16 ? 16 : 32) : base;
+    static constexpr int wpe = V ? DSORT_PAIR_GATHER_WPE : 1;
+    static_assert((E & (E - 1)) == 0 && CAP % E == 0 && CAP / E <= 1024, "bucket class shape");
 };
 constexpr int kGatherE = 16;
 
@@ -1310,7 +1341,7 @@ __global__ __launch_bounds__(CAP / 16) __attribute__((amdgpu_waves_per_eu(8))) v
 // items to a multiple of E, and sorted with the block merge sort.  One workgroup of CAP / E
 // threads per bucket of at most CAP items; persistent over the class's work list.
 template <class K, bool V, int CAP, bool XOUT, bool XIN = false>
-__global__ __launch_bounds__((CAP / GatherE<K, V, CAP>::E))
+__global__ __launch_bounds__((CAP / GatherE<K, V, CAP>::E), (GatherE<K, V, CAP>::wpe))
     void k_gather_bsort(GatherArgs a, uint32_t cls) {
     using R = Tr<K, V>;
     using T = typename R::T;
@@ -1372,7 +1403,7 @@ __global__ __launch_bounds__((CAP / GatherE<K, V, CAP>::E))
             }
         }
         __syncthreads();
-        block_sort<T, E>(lds, P);
+        block_sort<T, E, V>(lds, P);  // key/value elements carry their gathered position
 
         uint32_t pos[E];
 #pragma unroll
