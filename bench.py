@@ -138,6 +138,27 @@ def batched_leg(args, ds, torch, dev):
     for i in range(W, W + K):
         plan.sort_segmented(bufs[i], t_off, max_segment=max_seg, workspace=ws, stream=stream)
     torch.cuda.synchronize()
+    dt_default = (time.perf_counter() - t0) / K
+    plan.set_timing(False)
+    # autotune (L, s) per length class on the pristine batch, then time again
+    log("[bench] batched: autotuning")
+    t0 = time.perf_counter()
+    tuning = plan.autotune_segmented(src, t_off, max_segment=max_seg, repeats=2, workspace=ws,
+                                     stream=stream)
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t0
+    geo = plan.segmented_geometry(n, S, max_seg)
+    for b in bufs:
+        b.copy_(src)
+    for i in range(W):
+        plan.sort_segmented(bufs[i], t_off, max_segment=max_seg, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    log(f"[bench] batched: timing {K} tuned segmented calls")
+    t0 = time.perf_counter()
+    for i in range(W, W + K):
+        plan.sort_segmented(bufs[i], t_off, max_segment=max_seg, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / K
     stages = plan.stage_times()
     plan.set_timing(False)
@@ -176,9 +197,12 @@ def batched_leg(args, ds, torch, dev):
                     f"{args.batched_seed}), N(0,1) keys with 1% duplicates and signed zeros, "
                     f"IEEE totalOrder, keys only",
         "n": n, "segments": S, "max_segment": max_seg,
-        "L": geo.sublist_len, "s": geo.samples, "small_capacity": geo.small_capacity,
+        "small_capacity": geo.small_capacity,
+        "tuning": {"class_upper": geo.class_upper, "L": geo.sublist_len, "s": geo.samples},
+        "autotune_s": round(t_tune, 2),
         "value": round(n / dt / 1e6, 1), "unit": "Mkeys/s", "steps": K,
         "ms_per_step": round(dt * 1e3, 4),
+        "untuned_ms_per_step": round(dt_default * 1e3, 4),
         "back_to_back_mkeys_s": round(n / dtp / 1e6, 1),
         "back_to_back_ms": round(dtp * 1e3, 3),
         "speedup_vs_back_to_back": round(dtp / dt, 2),

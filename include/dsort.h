@@ -152,24 +152,69 @@ int dsort_segmented(dsort_plan_t plan, void *d_keys, uint32_t *d_values, uint64_
                     const uint64_t *d_offsets, uint64_t num_segments, uint64_t max_segment,
                     void *d_workspace, void *stream);
 
-/* Geometry of a segmented call with these sizes (see dsort_segmented). */
+/* Geometry of a segmented call with these sizes (see dsort_segmented), under the plan's
+ * current tuning.  Long segments (longer than small_capacity) are split by length into up to
+ * four classes; class c holds lengths in (class_upper[c-1], class_upper[c]] (class_upper[-1] =
+ * small_capacity) and runs one level of Algorithm 1 with its own L and s. */
 typedef struct {
     uint64_t n, num_segments;
-    uint64_t max_segment;        /* the bound used (after defaulting and clamping to n) */
-    uint64_t segment_limit;      /* longest segment this key layout accepts */
-    uint32_t small_capacity;     /* segments up to this size are sorted in one workgroup */
-    uint32_t max_long_segments;  /* bound on segments longer than small_capacity */
-    uint32_t sublist_len;        /* L for long segments (0 if there can be none) */
-    uint32_t samples;            /* s for long segments */
-    uint32_t max_sublists;       /* bound on sublists over all long segments */
-    uint32_t reserved;
-    uint64_t bucket_bound;       /* largest bucket of the longest admissible segment */
-    uint64_t off_status;         /* uint32 error flags raised by kernels (0 = none) */
-    uint64_t workspace_bytes;    /* bytes these sizes need (<= the plan's workspace size) */
+    uint64_t max_segment;           /* the bound used (after defaulting and clamping to n) */
+    uint64_t segment_limit;         /* longest segment this key layout accepts */
+    uint32_t small_capacity;        /* segments up to this size are sorted in one workgroup */
+    uint32_t classes;               /* long-segment classes with room for a segment */
+    uint64_t class_upper[4];
+    uint32_t sublist_len[4];        /* L of each class */
+    uint32_t samples[4];            /* s of each class */
+    uint32_t max_long_segments[4];  /* bound on the segments of each class */
+    uint32_t max_sublists[4];       /* bound on the sublists of each class */
+    uint64_t bucket_bound[4];       /* largest bucket of the longest segment of each class */
+    uint64_t off_status;            /* uint32 error flags raised by kernels (0 = none) */
+    uint64_t workspace_bytes;       /* bytes these sizes need (<= the plan's workspace size) */
 } dsort_seg_geometry_t;
 
 int dsort_segmented_geometry(dsort_plan_t plan, uint64_t n, uint64_t num_segments,
                              uint64_t max_segment, dsort_seg_geometry_t *out);
+
+/* Tuning of dsort_segmented's long segments, held by the plan.  classes = 0: one class with
+ * the defaults (L = the largest tile, s = the smallest power of two that keeps every bucket
+ * within one workgroup, Section 4's bound).  Otherwise class c (c < classes <= 4) holds lengths
+ * in (upper[c-1], upper[c]] (strictly increasing; the last class also takes every longer
+ * segment), with sublist_len[c] and samples[c] (0 = the defaults above).  Where a class's
+ * (L, s) cannot bound the buckets of its longest segment in a call, that call uses the
+ * defaults for the class.  Any tuning gives the same, unique, sorted result; it only changes
+ * the speed. */
+typedef struct {
+    uint32_t classes;
+    uint32_t reserved;
+    uint64_t upper[4];
+    uint32_t sublist_len[4];
+    uint32_t samples[4];
+} dsort_seg_tuning_t;
+
+/* Installs a tuning (NULL = the defaults).  Errors: DSORT_E_INVALID (bad plan, plan without
+ * segments, or bounds not increasing), DSORT_E_UNSUPPORTED (an L that is not a power of two
+ * in the tile range with at least 64 rows of items per thread, or an s that is not a power of
+ * two up to min(L, 1024)), DSORT_E_CAPACITY (the plan's workspace is too small for it; every
+ * tuning dsort_autotune_segmented can return fits). */
+int dsort_set_seg_tuning(dsort_plan_t plan, const dsort_seg_tuning_t *tuning);
+int dsort_get_seg_tuning(dsort_plan_t plan, dsort_seg_tuning_t *out);
+
+/* Autotuner: times candidate tunings on the caller's batch and installs the fastest.  The
+ * candidates for a set of lengths are the largest four tile lengths L (at least 64 rows of
+ * items per thread) and, for each, the smallest admissible s and its double and quadruple.
+ * (a) One class for all long segments: every candidate, timed on the whole batch, against the
+ * defaults.  (b) Length classes split at small_capacity times 4, 16 and 64: every candidate of
+ * a class timed on that class alone (the others at their defaults), the best per class
+ * combined and timed on the whole batch.  The fastest whole-batch time of (a) and (b) wins.
+ * Each run copies the batch (d_keys, d_values: left unchanged) into the caller's scratch
+ * buffers (n keys, and n values for key/value plans) and sorts there, `repeats` times (at least
+ * 1), timed with HIP events on `stream`.  Blocks until done.  Arguments as for dsort_segmented.
+ * On success *out (may be NULL) receives the tuning. */
+int dsort_autotune_segmented(dsort_plan_t plan, const void *d_keys, const uint32_t *d_values,
+                             uint64_t n, const uint64_t *d_offsets, uint64_t num_segments,
+                             uint64_t max_segment, void *d_scratch_keys,
+                             uint32_t *d_scratch_values, void *d_workspace, void *stream,
+                             uint32_t repeats, dsort_seg_tuning_t *out);
 
 /* ------------------------------------------------------------------------ served stream
  * A server sorts a stream of independent requests, each an array already in device memory

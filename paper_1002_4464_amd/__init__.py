@@ -13,7 +13,7 @@ from dataclasses import dataclass
 
 __all__ = [
     "U32", "U64", "F32", "DsortError", "Tuning", "Plan", "load_library", "sort", "sort_pairs",
-    "sort_segmented", "Server", "strerror", "EXPORTED_SYMBOLS",
+    "sort_segmented", "Server", "SegTuning", "strerror", "EXPORTED_SYMBOLS",
 ]
 
 U32, U64, F32 = 1, 2, 3
@@ -27,7 +27,8 @@ EXPORTED_SYMBOLS = (
     "dsort_plan_geometry", "dsort_set_timing", "dsort_stage_times", "dsort_last_error",
     "dsort_segmented", "dsort_segmented_geometry",
     "dsort_server_create", "dsort_submit", "dsort_poll", "dsort_release", "dsort_server_stats",
-    "dsort_server_destroy",
+    "dsort_server_destroy", "dsort_set_seg_tuning", "dsort_get_seg_tuning",
+    "dsort_autotune_segmented",
 )
 
 
@@ -62,11 +63,24 @@ class _Geometry(ctypes.Structure):
 class _SegGeometry(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint64), ("num_segments", ctypes.c_uint64),
                 ("max_segment", ctypes.c_uint64), ("segment_limit", ctypes.c_uint64),
-                ("small_capacity", ctypes.c_uint32), ("max_long_segments", ctypes.c_uint32),
-                ("sublist_len", ctypes.c_uint32), ("samples", ctypes.c_uint32),
-                ("max_sublists", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("bucket_bound", ctypes.c_uint64), ("off_status", ctypes.c_uint64),
-                ("workspace_bytes", ctypes.c_uint64)]
+                ("small_capacity", ctypes.c_uint32), ("classes", ctypes.c_uint32),
+                ("class_upper", ctypes.c_uint64 * 4), ("sublist_len", ctypes.c_uint32 * 4),
+                ("samples", ctypes.c_uint32 * 4), ("max_long_segments", ctypes.c_uint32 * 4),
+                ("max_sublists", ctypes.c_uint32 * 4), ("bucket_bound", ctypes.c_uint64 * 4),
+                ("off_status", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64)]
+
+
+class SegTuning(ctypes.Structure):
+    """Long-segment classes of segmented sorts: class c holds lengths in (upper[c-1], upper[c]]
+    with sublist length sublist_len[c] and samples[c] (0 = defaults); classes = 0: defaults."""
+    _fields_ = [("classes", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("upper", ctypes.c_uint64 * 4), ("sublist_len", ctypes.c_uint32 * 4),
+                ("samples", ctypes.c_uint32 * 4)]
+
+    def as_dict(self) -> dict:
+        c = self.classes
+        return {"classes": c, "upper": list(self.upper)[:c],
+                "sublist_len": list(self.sublist_len)[:c], "samples": list(self.samples)[:c]}
 
 
 class _Request(ctypes.Structure):
@@ -130,6 +144,13 @@ def load_library(path: str = LIB_PATH):
     lib.dsort_segmented.restype = I
     lib.dsort_segmented_geometry.argtypes = [P, U64_, U64_, U64_, ctypes.POINTER(_SegGeometry)]
     lib.dsort_segmented_geometry.restype = I
+    lib.dsort_set_seg_tuning.argtypes = [P, ctypes.POINTER(SegTuning)]
+    lib.dsort_set_seg_tuning.restype = I
+    lib.dsort_get_seg_tuning.argtypes = [P, ctypes.POINTER(SegTuning)]
+    lib.dsort_get_seg_tuning.restype = I
+    lib.dsort_autotune_segmented.argtypes = [P, P, P, U64_, P, U64_, U64_, P, P, P, P,
+                                             ctypes.c_uint32, ctypes.POINTER(SegTuning)]
+    lib.dsort_autotune_segmented.restype = I
     lib.dsort_server_create.argtypes = [ctypes.POINTER(P), U64_, ctypes.c_uint32,
                                         ctypes.c_uint32]
     lib.dsort_server_create.restype = I
@@ -188,12 +209,13 @@ class SegGeometry:
     max_segment: int
     segment_limit: int
     small_capacity: int
-    max_long_segments: int
-    sublist_len: int
-    samples: int
-    max_sublists: int
-    reserved: int
-    bucket_bound: int
+    classes: int
+    class_upper: list
+    sublist_len: list
+    samples: list
+    max_long_segments: list
+    max_sublists: list
+    bucket_bound: list
     off_status: int
     workspace_bytes: int
 
@@ -236,7 +258,48 @@ class Plan:
         _check(self._lib.dsort_segmented_geometry(self._h, int(n), int(num_segments),
                                                   int(max_segment), ctypes.byref(g)),
                "dsort_segmented_geometry")
-        return SegGeometry(*[getattr(g, f) for f, _ in _SegGeometry._fields_])
+        vals = []
+        for f, _ in _SegGeometry._fields_:
+            v = getattr(g, f)
+            vals.append(list(v)[:g.classes] if isinstance(v, ctypes.Array) else v)
+        return SegGeometry(*vals)
+
+    def set_seg_tuning(self, tuning: SegTuning | None):
+        _check(self._lib.dsort_set_seg_tuning(self._h, ctypes.byref(tuning) if tuning else None),
+               "dsort_set_seg_tuning")
+
+    def seg_tuning(self) -> SegTuning:
+        t = SegTuning()
+        _check(self._lib.dsort_get_seg_tuning(self._h, ctypes.byref(t)), "dsort_get_seg_tuning")
+        return t
+
+    def autotune_segmented(self, keys, offsets, values=None, max_segment: int = 0,
+                           repeats: int = 3, workspace=None, stream=None) -> SegTuning:
+        """Times candidate (L, s) per length class on this batch (left unchanged; scratch copies
+        are allocated here) and installs the fastest; returns the tuning."""
+        import torch
+        if (values is not None) != self.values:
+            raise ValueError("values must be given exactly for plans made with values")
+        ksz = 8 if self.key_type == U64 else 4
+        kp = self._dev_ptr(keys, ksz, "keys")
+        op = self._dev_ptr(offsets, 8, "offsets")
+        sk = torch.empty_like(keys)
+        vp = svp = None
+        sv = None
+        if values is not None:
+            vp = ctypes.c_void_p(self._dev_ptr(values, 4, "values"))
+            sv = torch.empty_like(values)
+            svp = ctypes.c_void_p(sv.data_ptr())
+        ws = workspace if workspace is not None else self.workspace(keys.device)
+        t = SegTuning()
+        rc = self._lib.dsort_autotune_segmented(
+            self._h, ctypes.c_void_p(kp), vp, keys.numel(), ctypes.c_void_p(op),
+            offsets.numel() - 1, int(max_segment), ctypes.c_void_p(sk.data_ptr()), svp,
+            ctypes.c_void_p(ws.data_ptr()), self._stream(stream, keys.device), int(repeats),
+            ctypes.byref(t))
+        _check(rc, "dsort_autotune_segmented")
+        del sk, sv
+        return t
 
     def set_timing(self, enable: bool):
         """Bracket every kernel launch of later calls with HIP events (clears the record)."""

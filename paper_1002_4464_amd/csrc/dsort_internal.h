@@ -55,18 +55,38 @@ struct Geom {
     size_t total = 0;
 };
 
-// Geometry of a segmented sort: S segments over n items, none longer than max_seg.  Segments
-// of at most small_cap items are sorted as one-piece buckets; the (at most gmax) longer ones
-// run one level of Algorithm 1 with sublists of L items and s samples each.
+// Segmented sorts: segments of at most small_cap items are sorted as one-piece buckets; the
+// longer ones are split by length into classes (lengths in (lo, hi]), each running one level of
+// Algorithm 1 with its own sublist length L and samples per sublist s.
+constexpr int kMaxSegClasses = 4;
+
+// Tuning of the long-segment classes.  classes = 0: one class with the defaults.  Class c holds
+// lengths in (upper[c-1], upper[c]] (upper[-1] = small_cap); the last class also takes every
+// longer segment.  L[c] = 0: the largest tile; s[c] = 0: the smallest s that bounds the buckets.
+struct SegTuning {
+    uint32_t classes = 0;
+    uint64_t upper[kMaxSegClasses] = {};
+    uint32_t L[kMaxSegClasses] = {};
+    uint32_t s[kMaxSegClasses] = {};
+};
+
+struct SegClassGeom {
+    uint64_t lo = 0, hi = 0;  // lengths in (lo, hi]
+    uint32_t L = 0, s = 0, gmax = 0, tiles_max = 0;
+    uint64_t beta = 0;        // bucket bound of a segment of hi items
+    size_t o_tab = 0, o_tileoff = 0;
+};
+
 struct SegGeom {
     int key_type = 0;
     bool values = false;
     uint64_t n = 0, S = 0, max_seg = 0;
     Caps caps{};
     uint32_t small_cap = 0;
-    uint32_t gmax = 0, L = 0, s = 0, tiles_max = 0;
-    uint64_t beta = 0;  // bucket bound of the longest admissible segment
-    size_t o_status = 0, o_segtab = 0, o_tileoff = 0, o_small_b = 0, o_spiece = 0, o_slists = 0;
+    uint32_t nclasses = 0;  // classes with room for at least one segment
+    SegClassGeom cls[kMaxSegClasses];
+    size_t o_status = 0, o_small_b = 0, o_spiece = 0, o_slists = 0;
+    // shared by the classes (they run one after the other)
     size_t o_wkeys = 0, o_wvals = 0, o_samp = 0, o_samp_sorted = 0, o_counts = 0, o_offs = 0;
     size_t o_pdst = 0, o_psrc = 0, o_final = 0, o_lists = 0;
     size_t total = 0;
@@ -104,9 +124,19 @@ int timing_summary(Timing &t, const char **names, float *avg_ms, uint32_t *launc
 
 // Enqueues the whole pipeline (kernels.hip).  Pointers are device pointers; tm may be null.
 int make_seg_geom(int key_type, bool values, uint64_t n, uint64_t S, uint64_t max_seg,
-                  SegGeom &g);
+                  const SegTuning &tu, SegGeom &g);
+// Smallest s for m sublists of L items (0 if none): buckets within one workgroup, samples
+// within the one-workgroup sample sort.
+uint64_t seg_samples(const Caps &c, uint64_t m, uint64_t L);
+// Workspace enough for every tuning the autotuner may pick (and the default one).
+size_t seg_workspace_bound(int key_type, bool values, uint64_t n, uint64_t S, uint64_t max_seg);
+// The class split the autotuner uses: lengths in (small_cap, 4 small_cap], (4, 16 small_cap], ...
+SegTuning seg_default_split(int key_type, bool values, uint64_t max_seg);
+// Candidate sublist lengths of the autotuner, largest first (count returned).
+int seg_candidate_L(const Caps &c, uint32_t *out);
+constexpr uint32_t kRunSmall = 1u << 31;  // run_segmented mask bit of the one-piece segments
 int run_segmented(const SegGeom &g, void *d_keys, uint32_t *d_vals, const uint64_t *d_off,
-                  void *d_ws, void *stream, Timing *tm);
+                  void *d_ws, void *stream, Timing *tm, uint32_t mask = 0xFFFFFFFFu);
 // Copies between requests' own buffers and a staging array (served-stream batches).
 int launch_pack(int key_bytes, const uint64_t *d_src_keys, const uint64_t *d_src_vals,
                 const uint64_t *d_off, uint32_t S, uint64_t total, void *stage_keys,
@@ -119,4 +149,25 @@ void set_last_error(const char *stage, const char *name, const char *text);
 
 constexpr uint64_t kMaxItems = (1ull << 32) - (1ull << 16);
 
+int plan_set_seg_tuning(dsort_plan_s *plan, const SegTuning &tu);
+
+}  // namespace dsort
+
+// Host state of a plan (dsort_plan_t).
+struct dsort_plan_s {
+    uint32_t magic;
+    int key_type;
+    int values;
+    uint64_t max_items;
+    uint64_t max_segments;
+    dsort_tuning_t tuning;
+    size_t workspace;
+    dsort::Geom last;  // geometry cache of the last n
+    dsort::Timing timing;
+    dsort::SegTuning seg_tuning;  // long-segment classes of dsort_segmented
+};
+
+namespace dsort {
+constexpr uint32_t kPlanMagic = 0x44534f52u;  // "DSOR"
+inline bool plan_valid(const dsort_plan_s *p) { return p && p->magic == kPlanMagic; }
 }  // namespace dsort

@@ -1440,27 +1440,34 @@ __global__ void k_init(uint32_t *status) {
     if (threadIdx.x <= 2u * kMaxClasses && blockIdx.x == 0) status[threadIdx.x] = 0;
 }
 
+// Long-segment classes of a segmented sort, as the set-up kernel sees them.
+struct SegClassArgs {
+    uint32_t n;                           // classes
+    uint32_t hi[kMaxSegClasses];          // class c: lengths in (hi[c-1], hi[c]]
+    uint32_t L[kMaxSegClasses];
+    uint32_t gmax[kMaxSegClasses];        // room in the class's tables
+    uint4 *tab[kMaxSegClasses];           // {begin, size, 0, 0} per segment of the class
+    uint32_t *tile_off[kMaxSegClasses];   // gmax + 1 entries
+};
+
 // Segmented sort set-up, one workgroup.  From the caller's CSR offsets (S + 1 uint64):
 //  * every segment that fits one workgroup (0 < size <= small_cap) becomes a one-piece bucket
 //    {begin, size, g, 1} on the work list of its size class;
-//  * the longer ones, in input order, form the compact segment table `large_tab` (at most gmax
-//    entries) and its tile map `tile_off` (ceil(size / L) tiles each, exclusive prefix); the
-//    unused entries up to gmax are empty segments with no tiles.
+//  * every longer one goes, in input order, to the compact table of its length class, with the
+//    class's tile map (ceil(size / L) tiles each, exclusive prefix); unused entries up to the
+//    class's room are empty segments with no tiles.
 // Offsets that decrease or pass n would let segments overlap or leave the array: then no
 // segment is sorted and status bit 16 is set.  A segment longer than max_seg is left as it is
 // and sets bit 32.
 __global__ __launch_bounds__(1024) void k_seg_prepare(const uint64_t *off, uint32_t S, uint32_t n,
-                                                      uint32_t max_seg, uint32_t L,
-                                                      uint32_t small_cap, uint32_t gmax,
-                                                      uint4 *large_tab, uint32_t *tile_off,
-                                                      uint4 *small_b, uint32_t *spiece,
-                                                      Classes cls, uint32_t *status) {
+                                                      uint32_t max_seg, uint32_t small_cap,
+                                                      SegClassArgs ca, uint4 *small_b,
+                                                      uint32_t *spiece, Classes cls,
+                                                      uint32_t *status) {
     __shared__ uint32_t wsum[17];
-    __shared__ uint32_t carry_t, carry_g, malformed;
-    if (threadIdx.x == 0) {
-        carry_t = carry_g = 0;
-        malformed = off[S] > n ? 1u : 0u;
-    }
+    __shared__ uint32_t carry_t[kMaxSegClasses], carry_g[kMaxSegClasses], malformed;
+    if (threadIdx.x < (uint32_t)kMaxSegClasses) carry_t[threadIdx.x] = carry_g[threadIdx.x] = 0;
+    if (threadIdx.x == 0) malformed = off[S] > n ? 1u : 0u;
     __syncthreads();
     for (uint32_t g = threadIdx.x; g < S; g += blockDim.x)
         if (off[g + 1] < off[g]) malformed = 1u;
@@ -1487,30 +1494,44 @@ __global__ __launch_bounds__(1024) void k_seg_prepare(const uint64_t *off, uint3
                 if (at < cls.stride) cls.list[(size_t)c * cls.stride + at] = g;
             }
         }
-        bool large = size > small_cap;
-        uint32_t tot_t, tot_g;
-        const uint32_t ex_g = block_excl_scan(large ? 1u : 0u, wsum, tot_g);
-        const uint32_t idx = carry_g + ex_g;
-        if (large && idx >= gmax) {  // cannot happen for disjoint segments inside [0, n)
-            atomicOr(status, 16u);
-            large = false;
+        uint32_t mine = kMaxSegClasses;  // length class of a long segment
+        if (size > small_cap) {
+            mine = 0;
+            while (mine + 1 < ca.n && size > ca.hi[mine]) ++mine;
         }
-        const uint32_t ex_t = block_excl_scan(large ? (size + L - 1) / L : 0u, wsum, tot_t);
-        if (large) {
-            large_tab[idx] = make_uint4(begin, size, 0u, 0u);
-            tile_off[idx] = carry_t + ex_t;
+        for (uint32_t c = 0; c < ca.n; ++c) {
+            bool in = mine == c;
+            uint32_t tot_t, tot_g;
+            const uint32_t ex_g = block_excl_scan(in ? 1u : 0u, wsum, tot_g);
+            const uint32_t idx = carry_g[c] + ex_g;
+            if (in && idx >= ca.gmax[c]) {  // cannot happen for disjoint segments inside [0, n)
+                atomicOr(status, 16u);
+                in = false;
+            }
+            const uint32_t ex_t =
+                block_excl_scan(in ? (size + ca.L[c] - 1) / ca.L[c] : 0u, wsum, tot_t);
+            if (in) {
+                ca.tab[c][idx] = make_uint4(begin, size, 0u, 0u);
+                ca.tile_off[c][idx] = carry_t[c] + ex_t;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                carry_t[c] += tot_t;
+                carry_g[c] = min(carry_g[c] + tot_g, ca.gmax[c]);
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            carry_t += tot_t;
-            carry_g = min(carry_g + tot_g, gmax);
-        }
-        __syncthreads();
     }
-    for (uint32_t i = carry_g + threadIdx.x; i <= gmax; i += blockDim.x) {
-        tile_off[i] = carry_t;
-        if (i < gmax) large_tab[i] = make_uint4(0u, 0u, 0u, 0u);
-    }
+    for (uint32_t c = 0; c < ca.n; ++c)
+        for (uint32_t i = carry_g[c] + threadIdx.x; i <= ca.gmax[c]; i += blockDim.x) {
+            ca.tile_off[c][i] = carry_t[c];
+            if (i < ca.gmax[c]) ca.tab[c][i] = make_uint4(0u, 0u, 0u, 0u);
+        }
+}
+
+// Clears the work-list counters of the final buckets (between the classes of a segmented sort).
+__global__ void k_clear_counters(uint32_t *count, uint32_t n) {
+    if (threadIdx.x < n) count[threadIdx.x] = 0;
 }
 
 // ------------------------------------------------------------------------------ host driver
@@ -1694,30 +1715,38 @@ template <class K, bool V, bool F32> struct Pipeline {
     // Algorithm 1 together (the segmented kernels of the second level), sublists sorted into the
     // workspace copy and gathered back per bucket.
     static int run_segmented(const SegGeom &g, void *d_keys, uint32_t *d_vals,
-                             const uint64_t *d_off, void *d_ws, hipStream_t st, Timing *tm) {
+                             const uint64_t *d_off, void *d_ws, hipStream_t st, Timing *tm,
+                             uint32_t mask) {
         char *ws = (char *)d_ws;
         uint32_t *status = (uint32_t *)(ws + g.o_status);
         DS_LAUNCH("init", k_init, dim3(1), dim3(64), status);
         K *keys = (K *)d_keys;
         const uint32_t n = (uint32_t)g.n;
         const uint32_t S = (uint32_t)g.S;
-        uint4 *large_tab = (uint4 *)(ws + g.o_segtab);
-        uint32_t *tile_off = (uint32_t *)(ws + g.o_tileoff);
         uint4 *small_b = (uint4 *)(ws + g.o_small_b);
         uint32_t *spiece = (uint32_t *)(ws + g.o_spiece);
         uint32_t *slists = (uint32_t *)(ws + g.o_slists);
         // counters of the one-piece classes follow those of the final buckets
         const Classes scls = classes(status + kMaxClasses, slists, S);
+        SegClassArgs ca{};
+        ca.n = g.nclasses;
+        for (uint32_t c = 0; c < g.nclasses; ++c) {
+            const SegClassGeom &q = g.cls[c];
+            ca.hi[c] = (uint32_t)q.hi;
+            ca.L[c] = q.L;
+            ca.gmax[c] = q.gmax;
+            ca.tab[c] = (uint4 *)(ws + q.o_tab);
+            ca.tile_off[c] = (uint32_t *)(ws + q.o_tileoff);
+        }
         DS_LAUNCH("seg_prepare", k_seg_prepare, dim3(1), dim3(1024), d_off, S, n,
-                  (uint32_t)g.max_seg, g.L, g.small_cap, g.gmax, large_tab, tile_off, small_b,
-                  spiece, scls, status);
-        {  // one-piece buckets in place: a workgroup reads its whole segment before writing
+                  (uint32_t)g.max_seg, g.small_cap, ca, small_b, spiece, scls, status);
+        if (mask & kRunSmall) {  // one-piece buckets in place: a workgroup reads its whole
+                                 // segment before writing
             GatherArgs a{keys, keys, d_vals, d_vals, small_b, spiece, spiece, scls.count, slists,
                          S, n, status};
             int rc0 = gather_classes<0, F32>(a, st, tm);
             if (rc0) return rc0;
         }
-        if (!g.gmax) return DSORT_OK;
         K *wkeys = (K *)(ws + g.o_wkeys);
         uint32_t *wvals = V ? (uint32_t *)(ws + g.o_wvals) : nullptr;
         SC *samp = (SC *)(ws + g.o_samp);
@@ -1728,23 +1757,33 @@ template <class K, bool V, bool F32> struct Pipeline {
         uint32_t *psrc = (uint32_t *)(ws + g.o_psrc);
         uint4 *finals = (uint4 *)(ws + g.o_final);
         uint32_t *lists = (uint32_t *)(ws + g.o_lists);
-        const Classes cls = classes(status, lists, g.gmax * g.s);
-        const SegView sv{large_tab, tile_off, g.gmax, 0, n, g.tiles_max};
-        {
-            TileArgs a{keys, wkeys, d_vals, wvals, sv, g.L, g.s, samp, status};
-            DS_LAUNCH("s123_local_sort", (k_tile<K, V, TE, TCAP, MODE_SAMPLE, F32, false>),
-                      dim3(g.tiles_max), dim3(g.L / TE), a);
+        bool first = true;
+        for (uint32_t c = 0; c < g.nclasses; ++c) {
+            const SegClassGeom &q = g.cls[c];
+            if (!(mask & (1u << c)) || q.gmax == 0) continue;
+            const Classes fcls = classes(status, lists, q.gmax * q.s);
+            if (!first) DS_LAUNCH("seg_clear", k_clear_counters, dim3(1), dim3(64), fcls.count,
+                                  (uint32_t)CC::n);
+            first = false;
+            const SegView sv{ca.tab[c], ca.tile_off[c], q.gmax, 0, n, q.tiles_max};
+            {
+                TileArgs a{keys, wkeys, d_vals, wvals, sv, q.L, q.s, samp, status};
+                DS_LAUNCH("s123_local_sort", (k_tile<K, V, TE, TCAP, MODE_SAMPLE, F32, false>),
+                          dim3(q.tiles_max), dim3(q.L / TE), a);
+            }
+            int rc = sort_samples(samp, sorted, nullptr, sv, q.L, q.s, q.gmax, 0, status, st,
+                                  false, 0, tm, "s4_sample_sort", "s4_sample_merge");
+            if (rc) return rc;
+            DS_LAUNCH("s56_rank", (k_rank<K, V>), dim3(q.tiles_max), dim3(256),
+                      (const K *)wkeys, (const void *)sorted, counts, sv, q.L, q.s);
+            DS_LAUNCH("s7_scan", k_scan_seg, dim3(q.gmax), dim3(256), (const uint32_t *)counts,
+                      offs, pdst, psrc, sv, q.L, q.s, finals, fcls);
+            GatherArgs a{wkeys, keys, wvals, d_vals, finals, pdst, psrc, fcls.count, lists,
+                         q.gmax * q.s, n, status};
+            rc = gather_classes<0>(a, st, tm);
+            if (rc) return rc;
         }
-        int rc = sort_samples(samp, sorted, nullptr, sv, g.L, g.s, g.gmax, 0, status, st, false,
-                              0, tm, "s4_sample_sort", "s4_sample_merge");
-        if (rc) return rc;
-        DS_LAUNCH("s56_rank", (k_rank<K, V>), dim3(g.tiles_max), dim3(256), (const K *)wkeys,
-                  (const void *)sorted, counts, sv, g.L, g.s);
-        DS_LAUNCH("s7_scan", k_scan_seg, dim3(g.gmax), dim3(256), (const uint32_t *)counts, offs,
-                  pdst, psrc, sv, g.L, g.s, finals, cls);
-        GatherArgs a{wkeys, keys, wvals, d_vals, finals, pdst, psrc, cls.count, lists,
-                     g.gmax * g.s, n, status};
-        return gather_classes<0>(a, st, tm);
+        return DSORT_OK;
     }
 
     static int run(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, hipStream_t st,
@@ -1957,24 +1996,27 @@ int launch_pack(int key_bytes, const uint64_t *d_src_keys, const uint64_t *d_src
 }
 
 int run_segmented(const SegGeom &g, void *d_keys, uint32_t *d_vals, const uint64_t *d_off,
-                  void *d_ws, void *stream, Timing *tm) {
+                  void *d_ws, void *stream, Timing *tm, uint32_t mask) {
     hipStream_t st = (hipStream_t)stream;
     if (g.S == 0 || g.n == 0) return DSORT_OK;
     (void)hipGetLastError();
     if (tm && !tm->enabled) tm = nullptr;
     switch (g.key_type) {
         case DSORT_U32:
-            return g.values
-                ? Pipeline<uint32_t, true, false>::run_segmented(g, d_keys, d_vals, d_off, d_ws, st, tm)
-                : Pipeline<uint32_t, false, false>::run_segmented(g, d_keys, d_vals, d_off, d_ws, st, tm);
+            return g.values ? Pipeline<uint32_t, true, false>::run_segmented(g, d_keys, d_vals,
+                                                                            d_off, d_ws, st, tm, mask)
+                            : Pipeline<uint32_t, false, false>::run_segmented(g, d_keys, d_vals,
+                                                                             d_off, d_ws, st, tm, mask);
         case DSORT_F32:
-            return g.values
-                ? Pipeline<uint32_t, true, true>::run_segmented(g, d_keys, d_vals, d_off, d_ws, st, tm)
-                : Pipeline<uint32_t, false, true>::run_segmented(g, d_keys, d_vals, d_off, d_ws, st, tm);
+            return g.values ? Pipeline<uint32_t, true, true>::run_segmented(g, d_keys, d_vals,
+                                                                           d_off, d_ws, st, tm, mask)
+                            : Pipeline<uint32_t, false, true>::run_segmented(g, d_keys, d_vals,
+                                                                            d_off, d_ws, st, tm, mask);
         case DSORT_U64:
-            return g.values
-                ? Pipeline<uint64_t, true, false>::run_segmented(g, d_keys, d_vals, d_off, d_ws, st, tm)
-                : Pipeline<uint64_t, false, false>::run_segmented(g, d_keys, d_vals, d_off, d_ws, st, tm);
+            return g.values ? Pipeline<uint64_t, true, false>::run_segmented(g, d_keys, d_vals,
+                                                                            d_off, d_ws, st, tm, mask)
+                            : Pipeline<uint64_t, false, false>::run_segmented(g, d_keys, d_vals,
+                                                                             d_off, d_ws, st, tm, mask);
         default:
             return DSORT_E_INVALID;
     }

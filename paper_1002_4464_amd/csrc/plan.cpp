@@ -8,6 +8,7 @@
 // 2n'/s - m <= capacity, which fixes the smallest admissible s.  When that s would make the
 // sample set too large (more than 1/32 of the data), Step 9 instead runs Algorithm 1 again on
 // each bucket (a second level), whose buckets then fit one workgroup.
+#include <algorithm>
 #include <new>
 #include <stdio.h>
 #include <stdlib.h>
@@ -203,27 +204,54 @@ int make_geom(int key_type, bool values, uint64_t n, const dsort_tuning_t &tu, G
     return DSORT_OK;
 }
 
-// Segmented sorts (one level).  A segment of z > small_cap items has m = ceil(z/L) sublists;
-// its s must keep every bucket within one workgroup (m (2L/s - 1) <= final_cap) and its m*s
-// samples within the one-workgroup sample sort (<= samp_cap).  Returns 0 if no s works.
-static uint64_t seg_samples(const Caps &c, uint64_t m) {
-    if (m > kMaxPieces) return 0;
-    const uint64_t L = c.tile_max;
+// Segmented sorts (one level per long segment).  A segment of z > small_cap items has
+// m = ceil(z/L) sublists; its s must keep every bucket within one workgroup
+// (m (2L/s - 1) <= final_cap, the bound of Section 4) and its m*s samples within the
+// one-workgroup sample sort (<= samp_cap).
+uint64_t seg_samples(const Caps &c, uint64_t m, uint64_t L) {
+    if (m == 0 || m > kMaxPieces) return 0;
     for (uint64_t s = 1; s <= L && s <= kMaxSamples; s <<= 1)
         if (bucket_bound(m, L, s) <= c.final_cap) return m * s <= c.samp_cap ? s : 0;
     return 0;
 }
 
+static bool seg_L_ok(const Caps &c, uint64_t L) {
+    return is_pow2(L) && L <= c.tile_max && L >= 64 * (uint64_t)c.tile_e;
+}
+
+int seg_candidate_L(const Caps &c, uint32_t *out) {
+    int k = 0;
+    for (uint64_t L = c.tile_max; k < 4 && seg_L_ok(c, L); L >>= 1) out[k++] = (uint32_t)L;
+    return k;
+}
+
 uint64_t seg_limit(int key_type, bool values) {
     const Caps c = caps_for(key_type, values);
     uint64_t m = 1;
-    while (m < kMaxPieces && seg_samples(c, m + 1)) ++m;
-    const uint64_t lim = seg_samples(c, m) ? m * c.tile_max : 0;
+    while (m < kMaxPieces && seg_samples(c, m + 1, c.tile_max)) ++m;
+    const uint64_t lim = seg_samples(c, m, c.tile_max) ? m * c.tile_max : 0;
     return lim > c.final_cap ? lim : c.final_cap;
 }
 
+static uint64_t clamp_max_seg(uint64_t n, uint64_t max_seg, uint64_t lim) {
+    if (max_seg == 0) max_seg = n < lim ? n : lim;
+    return max_seg > n ? n : max_seg;
+}
+
+SegTuning seg_default_split(int key_type, bool values, uint64_t max_seg) {
+    const Caps c = caps_for(key_type, values);
+    SegTuning t;
+    uint64_t hi = c.final_cap;
+    while (t.classes < (uint32_t)kMaxSegClasses) {
+        hi = t.classes + 1 == (uint32_t)kMaxSegClasses ? ~0ull : hi * 4;
+        t.upper[t.classes++] = hi;
+        if (hi >= max_seg) break;
+    }
+    return t;
+}
+
 int make_seg_geom(int key_type, bool values, uint64_t n, uint64_t S, uint64_t max_seg,
-                  SegGeom &g) {
+                  const SegTuning &tu, SegGeom &g) {
     g = SegGeom{};
     g.key_type = key_type;
     g.values = values;
@@ -231,23 +259,48 @@ int make_seg_geom(int key_type, bool values, uint64_t n, uint64_t S, uint64_t ma
     g.S = S;
     g.caps = caps_for(key_type, values);
     const Caps &c = g.caps;
-    if (n > kMaxItems) return DSORT_E_INVALID;
+    if (n > kMaxItems || tu.classes > (uint32_t)kMaxSegClasses) return DSORT_E_INVALID;
     const uint64_t lim = seg_limit(key_type, values);
-    if (max_seg == 0) max_seg = n < lim ? n : lim;
-    if (max_seg > n) max_seg = n;
+    max_seg = clamp_max_seg(n, max_seg, lim);
     if (max_seg > lim) return DSORT_E_UNSUPPORTED;
     g.max_seg = max_seg;
     g.small_cap = c.final_cap;
-    g.L = c.tile_max;
-    if (max_seg > g.small_cap) {
-        const uint64_t m = ceil_div(max_seg, g.L);
-        const uint64_t s = seg_samples(c, m);
-        if (!s) return DSORT_E_UNSUPPORTED;
-        g.s = (uint32_t)s;
-        g.beta = bucket_bound(m, g.L, s);
-        const uint64_t by_size = n / (g.small_cap + 1);
-        g.gmax = (uint32_t)(S < by_size ? S : by_size);
-        g.tiles_max = (uint32_t)(ceil_div(n, g.L) + g.gmax);
+    const uint32_t ncls = tu.classes ? tu.classes : 1u;
+    for (uint32_t k = 0, prev = 0; k < tu.classes; ++k) {  // bounds must increase
+        if (tu.upper[k] <= (k ? tu.upper[prev] : (uint64_t)g.small_cap)) return DSORT_E_INVALID;
+        prev = k;
+    }
+    uint64_t lo = g.small_cap;
+    for (uint32_t k = 0; k < ncls; ++k) {
+        const bool last = k + 1 == ncls;
+        uint64_t hi = last ? max_seg : (tu.upper[k] < max_seg ? tu.upper[k] : max_seg);
+        uint64_t L = tu.classes && tu.L[k] ? tu.L[k] : c.tile_max;
+        uint64_t s = tu.classes ? tu.s[k] : 0;
+        if (!seg_L_ok(c, L) || (s && (!is_pow2(s) || s > L || s > kMaxSamples)))
+            return DSORT_E_UNSUPPORTED;
+        if (hi > lo) {
+            uint64_t m = ceil_div(hi, L);
+            if (s && (m > kMaxPieces || bucket_bound(m, L, s) > c.final_cap ||
+                      m * s > c.samp_cap))
+                s = 0;  // cannot bound this call's buckets: this class uses the defaults
+            if (!s && !seg_samples(c, m, L)) {
+                L = c.tile_max;
+                m = ceil_div(hi, L);
+            }
+            if (!s) s = seg_samples(c, m, L);
+            if (!s) return DSORT_E_UNSUPPORTED;
+            SegClassGeom &q = g.cls[g.nclasses++];
+            q.lo = lo;
+            q.hi = hi;
+            q.L = (uint32_t)L;
+            q.s = (uint32_t)s;
+            q.beta = bucket_bound(m, L, s);
+            const uint64_t by_size = n / (lo + 1);
+            q.gmax = (uint32_t)(S < by_size ? S : by_size);
+            q.tiles_max = (uint32_t)(ceil_div(n, L) + q.gmax);
+        }
+        if (!last) lo = tu.upper[k] > lo ? tu.upper[k] : lo;
+        if (lo >= max_seg) break;
     }
     size_t off = 256;
     auto take = [&](size_t bytes) {
@@ -259,10 +312,15 @@ int make_seg_geom(int key_type, bool values, uint64_t n, uint64_t S, uint64_t ma
     g.o_small_b = take(S * 16);
     g.o_spiece = take(S * 4);
     g.o_slists = take(kNumClasses * S * 4);
-    g.o_segtab = take((size_t)g.gmax * 16);
-    g.o_tileoff = take(((size_t)g.gmax + 1) * 4);
-    if (g.gmax) {
-        const size_t sm = (size_t)g.tiles_max * g.s;
+    size_t sm = 0, fb = 0;
+    for (uint32_t k = 0; k < g.nclasses; ++k) {
+        SegClassGeom &q = g.cls[k];
+        q.o_tab = take((size_t)q.gmax * 16);
+        q.o_tileoff = take(((size_t)q.gmax + 1) * 4);
+        sm = std::max(sm, (size_t)q.tiles_max * q.s);
+        fb = std::max(fb, (size_t)q.gmax * q.s);
+    }
+    if (sm) {
         g.o_wkeys = take(n * c.key_bytes);
         if (values) g.o_wvals = take(n * 4);
         g.o_samp = take(sm * c.samp_bytes);
@@ -271,11 +329,42 @@ int make_seg_geom(int key_type, bool values, uint64_t n, uint64_t S, uint64_t ma
         g.o_offs = take(sm * 4);
         g.o_pdst = take(sm * 4);
         g.o_psrc = take(sm * 4);
-        g.o_final = take((size_t)g.gmax * g.s * 16);
-        g.o_lists = take(kNumClasses * (size_t)g.gmax * g.s * 4);
+        g.o_final = take(fb * 16);
+        g.o_lists = take(kNumClasses * fb * 4);
     }
     g.total = off;
     return DSORT_OK;
+}
+
+size_t seg_workspace_bound(int key_type, bool values, uint64_t n, uint64_t S, uint64_t max_seg) {
+    SegGeom g;
+    if (make_seg_geom(key_type, values, n, S, max_seg, SegTuning{}, g) != DSORT_OK) return 0;
+    size_t ws = g.total;
+    const Caps c = caps_for(key_type, values);
+    const SegTuning split = seg_default_split(key_type, values, g.max_seg);
+    uint32_t Ls[4];
+    const int nL = seg_candidate_L(c, Ls);
+    // Every trial of the autotuner changes one class to one (L, s) and leaves the others at
+    // their defaults; a final choice needs no more than the largest of its trials.
+    SegGeom h;
+    if (make_seg_geom(key_type, values, n, S, g.max_seg, split, h) == DSORT_OK)
+        ws = std::max(ws, h.total);
+    uint64_t lo = c.final_cap;
+    for (uint32_t k = 0; k < split.classes; ++k) {
+        const uint64_t hi = std::min<uint64_t>(split.upper[k], g.max_seg);
+        for (int i = 0; i < nL && hi > lo; ++i) {
+            const uint64_t s0 = seg_samples(c, ceil_div(hi, Ls[i]), Ls[i]);
+            for (uint64_t s = s0; s && s <= 4 * s0; s <<= 1) {
+                SegTuning one = split;
+                one.L[k] = Ls[i];
+                one.s[k] = (uint32_t)s;
+                if (make_seg_geom(key_type, values, n, S, g.max_seg, one, h) == DSORT_OK)
+                    ws = std::max(ws, h.total);
+            }
+        }
+        lo = split.upper[k];
+    }
+    return ws;
 }
 
 static thread_local char g_last_error[256];
@@ -291,21 +380,7 @@ void set_last_error(const char *stage, const char *name, const char *text) {
 
 using dsort::Geom;
 
-struct dsort_plan_s {
-    uint32_t magic;
-    int key_type;
-    int values;
-    uint64_t max_items;
-    uint64_t max_segments;
-    dsort_tuning_t tuning;
-    size_t workspace;
-    Geom last;  // geometry cache of the last n
-    dsort::Timing timing;
-};
-
-static constexpr uint32_t kMagic = 0x44534f52u;  // "DSOR"
-
-static bool plan_ok(const dsort_plan_s *p) { return p && p->magic == kMagic; }
+static bool plan_ok(const dsort_plan_s *p) { return dsort::plan_valid(p); }
 
 static int geom_for(dsort_plan_s *p, uint64_t n, const Geom **out) {
     if (p->last.n != n || p->last.levels == -2) {
@@ -365,18 +440,19 @@ int dsort_plan(dsort_plan_t *out, int key_type, int with_values, uint64_t max_it
             lo = a + 1;
         }
     }
-    // Segmented calls: every buffer grows with n, S and the longest admissible segment.
+    // Segmented calls: every buffer grows with n, S and the longest admissible segment; the
+    // bound also covers every tuning the autotuner may choose.
     if (max_segments && max_items) {
         const uint64_t lim = dsort::seg_limit(key_type, with_values != 0);
-        dsort::SegGeom sg;
-        if (dsort::make_seg_geom(key_type, with_values != 0, max_items, max_segments,
-                                 max_items < lim ? max_items : lim, sg) != DSORT_OK)
-            return DSORT_E_UNSUPPORTED;
-        if (sg.total > ws) ws = sg.total;
+        const size_t sw = dsort::seg_workspace_bound(key_type, with_values != 0, max_items,
+                                                     max_segments,
+                                                     max_items < lim ? max_items : lim);
+        if (!sw) return DSORT_E_UNSUPPORTED;
+        if (sw > ws) ws = sw;
     }
     dsort_plan_s *p = new (std::nothrow) dsort_plan_s{};
     if (!p) return DSORT_E_NOMEM;
-    p->magic = kMagic;
+    p->magic = dsort::kPlanMagic;
     p->key_type = key_type;
     p->values = with_values;
     p->max_items = max_items;
@@ -476,7 +552,8 @@ static int seg_geom_for(dsort_plan_t plan, uint64_t n, uint64_t S, uint64_t max_
                         dsort::SegGeom &g) {
     if (!plan_ok(plan)) return DSORT_E_INVALID;
     if (n > plan->max_items || S > plan->max_segments) return DSORT_E_INVALID;
-    return dsort::make_seg_geom(plan->key_type, plan->values != 0, n, S, max_segment, g);
+    return dsort::make_seg_geom(plan->key_type, plan->values != 0, n, S, max_segment,
+                                plan->seg_tuning, g);
 }
 
 int dsort_segmented_geometry(dsort_plan_t plan, uint64_t n, uint64_t num_segments,
@@ -491,13 +568,73 @@ int dsort_segmented_geometry(dsort_plan_t plan, uint64_t n, uint64_t num_segment
     out->max_segment = g.max_seg;
     out->segment_limit = dsort::seg_limit(plan->key_type, plan->values != 0);
     out->small_capacity = g.small_cap;
-    out->max_long_segments = g.gmax;
-    out->sublist_len = g.L;
-    out->samples = g.s;
-    out->max_sublists = g.tiles_max;
-    out->bucket_bound = g.beta;
+    out->classes = g.nclasses;
+    for (uint32_t c = 0; c < g.nclasses; ++c) {
+        const dsort::SegClassGeom &q = g.cls[c];
+        out->class_upper[c] = q.hi;
+        out->sublist_len[c] = q.L;
+        out->samples[c] = q.s;
+        out->max_long_segments[c] = q.gmax;
+        out->max_sublists[c] = q.tiles_max;
+        out->bucket_bound[c] = q.beta;
+    }
     out->off_status = g.o_status;
     out->workspace_bytes = g.total;
+    return DSORT_OK;
+}
+
+static dsort::SegTuning tuning_from(const dsort_seg_tuning_t &t) {
+    dsort::SegTuning s;
+    s.classes = t.classes;
+    for (int c = 0; c < dsort::kMaxSegClasses; ++c) {
+        s.upper[c] = t.upper[c];
+        s.L[c] = t.sublist_len[c];
+        s.s[c] = t.samples[c];
+    }
+    return s;
+}
+
+static void tuning_to(const dsort::SegTuning &s, dsort_seg_tuning_t &t) {
+    memset(&t, 0, sizeof(t));
+    t.classes = s.classes;
+    for (int c = 0; c < dsort::kMaxSegClasses; ++c) {
+        t.upper[c] = s.upper[c];
+        t.sublist_len[c] = s.L[c];
+        t.samples[c] = s.s[c];
+    }
+}
+
+extern "C++" {
+namespace dsort {
+// Checks a tuning against the plan's largest call and installs it.
+int plan_set_seg_tuning(dsort_plan_s *plan, const SegTuning &tu) {
+    const uint64_t lim = seg_limit(plan->key_type, plan->values != 0);
+    SegGeom g;
+    const int rc = make_seg_geom(plan->key_type, plan->values != 0, plan->max_items,
+                                 plan->max_segments,
+                                 plan->max_items < lim ? plan->max_items : lim, tu, g);
+    if (rc != DSORT_OK) return rc;
+    if (g.total > plan->workspace) return DSORT_E_CAPACITY;
+    plan->seg_tuning = tu;
+    return DSORT_OK;
+}
+}  // namespace dsort
+}
+
+int dsort_set_seg_tuning(dsort_plan_t plan, const dsort_seg_tuning_t *tuning) {
+    if (!plan_ok(plan)) return DSORT_E_INVALID;
+    if (!tuning) {
+        plan->seg_tuning = dsort::SegTuning{};
+        return DSORT_OK;
+    }
+    if (tuning->classes > (uint32_t)dsort::kMaxSegClasses) return DSORT_E_INVALID;
+    if (!plan->max_segments) return DSORT_E_INVALID;
+    return dsort::plan_set_seg_tuning(plan, tuning_from(*tuning));
+}
+
+int dsort_get_seg_tuning(dsort_plan_t plan, dsort_seg_tuning_t *out) {
+    if (!plan_ok(plan) || !out) return DSORT_E_INVALID;
+    tuning_to(plan->seg_tuning, *out);
     return DSORT_OK;
 }
 

@@ -76,7 +76,7 @@ class HipExecutor : public srv::Executor {
         const uint64_t S = u.reqs.size();
         if (S > max_req_) return 0;
         SegGeom sg;
-        if (make_seg_geom(u.key_type, u.values, u.total, S, u.max_seg, sg) != DSORT_OK) return 0;
+        if (make_seg_geom(u.key_type, u.values, u.total, S, u.max_seg, SegTuning{}, sg) != DSORT_OK) return 0;
         size_t b = al256(sg.total);
         b += al256(u.total * key_bytes_of(u.key_type));
         if (u.values) b += al256(u.total * 4);
@@ -99,7 +99,7 @@ class HipExecutor : public srv::Executor {
         } else {
             const uint32_t S = (uint32_t)u.reqs.size();
             SegGeom sg;
-            rc = make_seg_geom(u.key_type, u.values, u.total, S, u.max_seg, sg);
+            rc = make_seg_geom(u.key_type, u.values, u.total, S, u.max_seg, SegTuning{}, sg);
             if (rc != DSORT_OK) return rc;
             char *p = blk + al256(sg.total);
             void *stage_keys = p;

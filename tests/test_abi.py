@@ -116,11 +116,28 @@ def test_workspace_covers_all_smaller_sizes():
             assert p.geometry(n).workspace_bytes <= p.workspace_bytes
 
 
+def _check_seg_geometry(g, n, S):
+    """Every long class runs one level of Algorithm 1: for its longest segment (m sublists) the
+    bucket bound m(2L/s - 1) fits one workgroup and the m*s samples fit the one-workgroup
+    sample sort."""
+    lo = g.small_capacity
+    for c in range(g.classes):
+        L, s, hi = g.sublist_len[c], g.samples[c], g.class_upper[c]
+        assert hi > lo and L & (L - 1) == 0 and s & (s - 1) == 0
+        m = -(-hi // L)
+        assert g.bucket_bound[c] == m * (2 * L // s - 1) <= g.small_capacity
+        assert m * s <= 16384
+        assert g.max_long_segments[c] == min(S, n // (lo + 1))
+        assert g.max_sublists[c] >= -(-n // L)
+        lo = hi
+    if g.classes:
+        assert g.class_upper[-1] == g.max_segment
+
+
 @pytest.mark.parametrize("kt,values", [(1, False), (1, True), (2, False), (2, True), (3, False)])
 def test_segmented_geometry_invariants(kt, values):
-    """Long segments run one level of Algorithm 1: for the longest admissible segment (m
-    sublists) the bucket bound m(2L/s - 1) fits one workgroup and the m*s samples fit the
-    one-workgroup sample sort; the plan's workspace covers every smaller batch."""
+    """Default tuning: one long class; s the smallest admissible; the plan's workspace covers
+    every smaller batch."""
     n = 1 << 24
     p = ds.Plan(kt, values, n, max_segments=4096)
     lim = p.segmented_geometry(n, 4096).segment_limit
@@ -131,21 +148,64 @@ def test_segmented_geometry_invariants(kt, values):
             assert g.workspace_bytes <= p.workspace_bytes
             assert g.max_segment == (min(n, lim) if max_seg == 0 else max_seg)
             if g.max_segment <= g.small_capacity:
-                assert g.max_long_segments == 0
+                assert g.classes == 0
                 continue
-            L, s = g.sublist_len, g.samples
+            assert g.classes == 1
+            _check_seg_geometry(g, n, S)
+            L, s = g.sublist_len[0], g.samples[0]
             m = -(-g.max_segment // L)
-            assert g.bucket_bound == m * (2 * L // s - 1) <= g.small_capacity
-            assert s == 1 or m * (2 * L // (s // 2) - 1) > g.small_capacity or \
-                m * s > 8192  # s is the smallest that works, unless the samples cap binds
-            assert g.max_long_segments == min(S, n // (g.small_capacity + 1))
-            assert g.max_sublists >= -(-n // L)
+            assert s == 1 or m * (2 * L // (s // 2) - 1) > g.small_capacity
     with pytest.raises(ds.DsortError) as e:
         p.segmented_geometry(n, 10, lim + 1)
     assert e.value.status == ds.E_UNSUPPORTED
     with pytest.raises(ds.DsortError) as e:
         p.segmented_geometry(n, 4097, 0)
     assert e.value.status == ds.E_INVALID
+
+
+def _tuning(classes, upper, L, s):
+    t = ds.SegTuning()
+    t.classes = classes
+    for i in range(classes):
+        t.upper[i], t.sublist_len[i], t.samples[i] = upper[i], L[i], s[i]
+    return t
+
+
+@pytest.mark.parametrize("kt,values", [(1, False), (1, True), (2, True), (3, False)])
+def test_segmented_tuning_classes(kt, values):
+    """Tunings the autotuner can pick fit the plan's workspace; the geometry follows them."""
+    n = 1 << 24
+    p = ds.Plan(kt, values, n, max_segments=4096)
+    lim = p.segmented_geometry(n, 4096).segment_limit
+    cap = p.segmented_geometry(n, 4096).small_capacity
+    upper = [cap * 4, cap * 16, cap * 64, 1 << 62]
+    for L in (2048, 4096, 8192):
+        for mult in (1, 2):
+            t = _tuning(4, upper, [L, L, 0, 0], [0, 0, 0, 0])
+            p.set_seg_tuning(t)
+            g = p.segmented_geometry(n, 4096, lim)
+            assert g.workspace_bytes <= p.workspace_bytes
+            _check_seg_geometry(g, n, 4096)
+            assert g.sublist_len[0] == L
+    p.set_seg_tuning(None)
+    assert p.seg_tuning().classes == 0
+    # infeasible or malformed tunings are refused and leave the tuning unchanged
+    with pytest.raises(ds.DsortError) as e:
+        p.set_seg_tuning(_tuning(2, [cap * 4, cap * 2], [0, 0], [0, 0]))
+    assert e.value.status == ds.E_INVALID
+    with pytest.raises(ds.DsortError) as e:
+        p.set_seg_tuning(_tuning(1, [1 << 62], [3000], [0]))
+    assert e.value.status == ds.E_UNSUPPORTED
+    with pytest.raises(ds.DsortError) as e:
+        p.set_seg_tuning(_tuning(1, [1 << 62], [0], [3]))  # s not a power of two
+    assert e.value.status == ds.E_UNSUPPORTED
+    assert p.seg_tuning().classes == 0
+    # an (L, s) that cannot bound a call's buckets falls back to the defaults for that call
+    p.set_seg_tuning(_tuning(2, [cap * 4, 1 << 62], [2048, 2048], [1, 1]))
+    g = p.segmented_geometry(n, 4096, lim)
+    _check_seg_geometry(g, n, 4096)
+    default = ds.Plan(kt, values, n, max_segments=4096).segmented_geometry(n, 4096, lim)
+    assert g.samples[-1] == default.samples[0] and g.sublist_len[-1] == default.sublist_len[0]
 
 
 def test_segmented_rejects_bad_arguments_without_gpu():

@@ -83,7 +83,7 @@ def test_u32_keys_edge_sizes(ds):
     say("[seg] u32 keys", len(sizes), "segments, n =", n)
     out, _, geo = gpu_segmented(ds, keys, offs)
     want, _ = oracle.segmented_sort(keys, offs)
-    assert geo.max_long_segments > 0
+    assert geo.classes == 1 and geo.max_long_segments[0] > 0
     assert (out == want).all()
 
 
@@ -161,7 +161,7 @@ def test_tight_bound_same_result(ds):
     plan = ds.Plan(1, False, n, max_segments=len(sizes))
     g_loose = plan.segmented_geometry(n, len(sizes), 0)
     g_tight = plan.segmented_geometry(n, len(sizes), int(sizes.max()))
-    assert g_tight.samples <= g_loose.samples
+    assert g_tight.samples[0] <= g_loose.samples[0]
     a, _, _ = gpu_segmented(ds, keys, offs, plan=plan)
     b, _, _ = gpu_segmented(ds, keys, offs, plan=plan, max_segment=int(sizes.max()))
     want, _ = oracle.segmented_sort(keys, offs)
@@ -277,3 +277,75 @@ def test_full_batched_workload(ds):
         want, _ = oracle.stable_sort(x[lo:hi])
         got = tk[lo:hi].cpu().numpy().view(np.float32)
         assert (got.view(np.uint32) == want.view(np.uint32)).all(), f"segment {g}"
+
+
+def _tuning(ds, upper, L, s):
+    t = ds.SegTuning()
+    t.classes = len(upper)
+    for i in range(len(upper)):
+        t.upper[i], t.sublist_len[i], t.samples[i] = upper[i], L[i], s[i]
+    return t
+
+
+@pytest.mark.parametrize("kt,pairs", [(1, False), (1, True), (2, True), (3, False)])
+def test_tuned_classes_parity(ds, kt, pairs):
+    """Long segments split into four length classes, each with its own sublist length and
+    samples per sublist (including non-default ones), sort to the oracle's result; segment
+    lengths sit on both sides of every class bound."""
+    dt = {1: np.uint32, 2: np.uint64, 3: np.float32}[kt]
+    probe = ds.Plan(kt, pairs, 1 << 16, max_segments=1)
+    cap = probe.segmented_geometry(1 << 16, 1).small_capacity
+    lim = probe.segmented_geometry(1 << 16, 1).segment_limit
+    upper = [cap * 4, cap * 16, cap * 64, 1 << 62]
+    sizes = [0, 5, cap, cap + 1, 3 * cap, cap * 4, cap * 4 + 1, cap * 10, cap * 16,
+             cap * 16 + 7, min(lim, cap * 40), 77, min(lim, cap * 64 + 1)]
+    offs, n = offsets_of(sizes, [2] * len(sizes))
+    n += 3
+    if kt == 3:
+        keys = synth.normal_f32_segments(np.array([n]), 41, dup_frac=0.05, zero_log2=8)
+    elif kt == 2:
+        keys = synth.zipf_u64(n, 41)
+    else:
+        keys = synth.make_u32("bucket", n, 41)
+    vals = synth.index_values(n) if pairs else None
+    plan = ds.Plan(kt, pairs, n, max_segments=len(sizes))
+    tl = plan.segmented_geometry(n, len(sizes)).sublist_len[0]
+    Ls = [tl // 8, tl // 4, tl, tl]
+    plan.set_seg_tuning(_tuning(ds, upper, Ls, [0, 0, 0, 0]))
+    geo = plan.segmented_geometry(n, len(sizes))
+    say("[seg] tuned classes", kt, pairs, "n =", n, "L =", geo.sublist_len, "s =", geo.samples)
+    assert geo.classes >= 3
+    out_k, out_v, _ = gpu_segmented(ds, keys, offs, vals, plan=plan)
+    want_k, want_v = oracle.segmented_sort(keys, offs, vals)
+    assert (out_k.view(np.uint8) == want_k.view(np.uint8)).all()
+    if pairs:
+        assert (out_v == want_v).all()
+    # doubled samples per sublist in the two shorter classes: same result
+    t = _tuning(ds, upper, Ls, [2 * geo.samples[0], 2 * geo.samples[1], 0, 0])
+    plan.set_seg_tuning(t)
+    out_k2, out_v2, _ = gpu_segmented(ds, keys, offs, vals, plan=plan)
+    assert (out_k2.view(np.uint8) == want_k.view(np.uint8)).all()
+    if pairs:
+        assert (out_v2 == want_v).all()
+
+
+def test_autotune_installs_and_keeps_input(ds):
+    """The autotuner leaves the batch unchanged, installs a feasible tuning per length class,
+    and sorts under it give the oracle's result."""
+    import torch
+    sizes = synth.segment_sizes(200, 61, 8, 20)
+    offs, n = offsets_of(sizes)
+    keys = synth.uniform_u32(n, 61)
+    plan = ds.Plan(1, False, n, max_segments=sizes.size)
+    tk = to_dev(keys)
+    to = torch.from_numpy(offs).cuda()
+    t = plan.autotune_segmented(tk, to, max_segment=int(sizes.max()), repeats=2)
+    torch.cuda.synchronize()
+    say("[seg] autotuned", t.as_dict())
+    assert (from_dev(tk, np.uint32) == keys).all(), "autotuning must not touch the batch"
+    assert t.classes >= 1 and plan.seg_tuning().as_dict() == t.as_dict()
+    assert all(L > 0 and s > 0 for L, s in zip(t.as_dict()["sublist_len"],
+                                                t.as_dict()["samples"]))
+    out, _, _ = gpu_segmented(ds, keys, offs, plan=plan, max_segment=int(sizes.max()))
+    want, _ = oracle.segmented_sort(keys, offs)
+    assert (out == want).all()
