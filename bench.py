@@ -362,10 +362,15 @@ def ingest_pmc(fetch_csv: str, write_csv: str, copy_bytes: int, sorts: int, out_
     res = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = load(path, counter)
+        last_sort = max((int(r["Dispatch_Id"]) for r in rows if "dsort" in r["Kernel_Name"]),
+                        default=0)
         copies = [float(r["Counter_Value"]) * 1024 for r in rows
-                  if "copyBuffer" in r["Kernel_Name"] or "elementwise" in r["Kernel_Name"]]
-        # the calibration copy is the last copy kernel in the run
-        scale = copy_bytes / copies[-1] if copies and copies[-1] > 0 else 1.0
+                  if int(r["Dispatch_Id"]) > last_sort and
+                  ("copyBuffer" in r["Kernel_Name"] or "elementwise" in r["Kernel_Name"])]
+        # the calibration copy is the largest copy kernel after the sorts (the others are the
+        # small device-to-host reads of the result checks)
+        big = max(copies, default=0.0)
+        scale = copy_bytes / big if big > 0 else 1.0
         per = collections.defaultdict(float)
         seen = {}
         started = False
