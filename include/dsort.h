@@ -37,7 +37,7 @@ enum {
 enum {
     DSORT_OK = 0,
     DSORT_E_INVALID = -1,     /* bad argument: NULL pointer, unknown type, n > plan maximum, ... */
-    DSORT_E_UNSUPPORTED = -2, /* valid request this build cannot serve (e.g. tuning infeasible) */
+    DSORT_E_UNSUPPORTED = -2, /* valid request the library cannot serve (e.g. tuning infeasible) */
     DSORT_E_NOMEM = -3,       /* host allocation failed */
     DSORT_E_HIP = -4,         /* a HIP runtime call or kernel launch failed */
     DSORT_E_CAPACITY = -5,    /* request larger than a configured capacity */
