@@ -749,30 +749,46 @@ __global__ __launch_bounds__(CAP / E) void k_merge_round(const SC *src, SC *dst,
 
 // One workgroup per sublist; lane j locates global sample g_j = S[(j+1) m - 1] of the
 // sublist's segment: r_ij = #{x : (A_i[x], i*L + x) <= g_j}, a monotone predicate on the
-// sorted sublist, found by bisection in global memory (the first probes, shared by all lanes,
-// hit the caches).  Pads (x >= count) are key-max items.
+// sorted sublist.  The sublist's own Step-3 samples (the items at ranks (k+1) w - 1, w = L/s)
+// narrow it first: if c of them are <= g_j, then c w <= r_ij <= (c+1) w - 1, so a bisection
+// over the s samples in LDS leaves one of log2(w) probes in global memory.  Pads (x >= count)
+// are key-max items.
 template <class K, bool V>
 __global__ __launch_bounds__(256) void k_rank(const K *keys, const void *sorted_samples,
-                                              uint32_t *counts, SegView sv, uint32_t L,
-                                              uint32_t s) {
+                                              const void *tile_samples, uint32_t *counts,
+                                              SegView sv, uint32_t L, uint32_t s) {
     using R = Tr<K, V>;
     using SC = typename R::SC;
     __shared__ uint32_t rk[1025];
+    __shared__ SC ts[1024];
     TileLoc loc;
     if (!locate_tile(sv, L, blockIdx.x, loc)) return;
     const uint32_t base = loc.seg_begin + loc.i * L;
     const uint32_t count = min(L, loc.seg_size - loc.i * L);
     const SC *S = (const SC *)sorted_samples + (size_t)loc.tile0 * s;
+    const SC *T = (const SC *)tile_samples + (size_t)(loc.tile0 + loc.i) * s;
+    for (uint32_t k = threadIdx.x; k < s; k += blockDim.x) ts[k] = T[k];
+    __syncthreads();
     const uint32_t p0 = loc.i * L;
+    const uint32_t w = L / s;
     for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) {
         const SC g = S[(size_t)(j + 1) * loc.m - 1];
-        uint32_t lo = 0, hi = L;
+        uint32_t lo = 0, hi = s;  // c = #{k : sample_k <= g}
         while (lo < hi) {
-            const uint32_t x = (lo + hi) >> 1;
-            const K kx = x < count ? keys[base + x] : KeyMax<K>::v;
-            if (!lt(g, R::samp(kx, p0 + x))) lo = x + 1; else hi = x;
+            const uint32_t mid = (lo + hi) >> 1;
+            if (!lt(g, ts[mid])) lo = mid + 1; else hi = mid;
         }
-        rk[j + 1] = lo;
+        uint32_t r = L;
+        if (lo < s) {
+            uint32_t a = lo * w, b = (lo + 1) * w - 1;
+            while (a < b) {
+                const uint32_t x = (a + b) >> 1;
+                const K kx = x < count ? keys[base + x] : KeyMax<K>::v;
+                if (!lt(g, R::samp(kx, p0 + x))) a = x + 1; else b = x;
+            }
+            r = a;
+        }
+        rk[j + 1] = r;
     }
     if (threadIdx.x == 0) rk[0] = 0;
     __syncthreads();
@@ -1775,7 +1791,8 @@ template <class K, bool V, bool F32> struct Pipeline {
                                   false, 0, tm, "s4_sample_sort", "s4_sample_merge");
             if (rc) return rc;
             DS_LAUNCH("s56_rank", (k_rank<K, V>), dim3(q.tiles_max), dim3(256),
-                      (const K *)wkeys, (const void *)sorted, counts, sv, q.L, q.s);
+                      (const K *)wkeys, (const void *)sorted, (const void *)samp, counts, sv,
+                      q.L, q.s);
             DS_LAUNCH("s7_scan", k_scan_seg, dim3(q.gmax), dim3(256), (const uint32_t *)counts,
                       offs, pdst, psrc, sv, q.L, q.s, finals, fcls);
             GatherArgs a{wkeys, keys, wvals, d_vals, finals, pdst, psrc, fcls.count, lists,
@@ -1837,7 +1854,7 @@ template <class K, bool V, bool F32> struct Pipeline {
         if (rc) return rc;
         // Steps 5-6
         DS_LAUNCH("s56_rank", (k_rank<K, V>), dim3(g.m1), dim3(256), (const K *)tiles,
-                  (const void *)sorted, counts, sv1, g.L1, g.s1);
+                  (const void *)sorted, (const void *)samp, counts, sv1, g.L1, g.s1);
         // Step 7
         DS_LAUNCH("s7_scan_colsum", k_scan_partial, dim3(g.scan_nrb), dim3(256),
                   (const uint32_t *)counts, partial, g.m1, g.s1, g.scan_rb);
@@ -1884,7 +1901,7 @@ template <class K, bool V, bool F32> struct Pipeline {
                           tm, "l2_s4_sample_sort", "l2_s4_sample_merge");
         if (rc) return rc;
         DS_LAUNCH("l2_s56_rank", (k_rank<K, V>), dim3(g.tiles2max), dim3(256), (const K *)wkeys,
-                  (const void *)sorted2, counts2, sv2, g.L2, g.s2);
+                  (const void *)sorted2, (const void *)samp2, counts2, sv2, g.L2, g.s2);
         DS_LAUNCH("l2_s7_scan", k_scan_seg, dim3(g.s1), dim3(256), (const uint32_t *)counts2,
                   offs2, pdst2, psrc2, sv2, g.L2, g.s2, finals, cls);
         GatherArgs a{wkeys, keys, wvals, d_vals, finals, pdst2, psrc2, status + 1, lists,
