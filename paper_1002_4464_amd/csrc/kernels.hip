@@ -718,14 +718,25 @@ __global__ __launch_bounds__(CAP / E) void k_merge_round(const SC *src, SC *dst,
     const uint32_t b0 = a1, b1 = min(pb + 2 * R, total);
     const uint32_t na = a1 - a0, nb = b1 - b0;
     const uint32_t d0 = c0 - pb, d1 = min(d0 + CAP, na + nb);
-    if (tid < 2) {
-        const uint32_t d = tid ? d1 : d0;
+    if (tid < 128) {  // wave 0 finds the split of d0, wave 1 that of d1, 64 probes per round
+        const uint32_t lane = tid & 63;
+        const uint32_t d = (tid >> 6) ? d1 : d0;
         uint32_t lo = d > nb ? d - nb : 0, hi = min(d, na);
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (mlt<true>(src[b0 + d - 1 - mid], src[a0 + mid])) hi = mid; else lo = mid + 1;
+        while (lo < hi) {  // smallest x in [lo, hi) with B[d-1-x] < A[x], else hi
+            const uint32_t step = (hi - lo + 63) >> 6;
+            const uint32_t x = lo + lane * step;
+            const bool pr = x >= hi || mlt<true>(src[b0 + d - 1 - x], src[a0 + x]);
+            const uint64_t m = __ballot(pr);
+            if (m == 0) {
+                lo = lo + 63 * step + 1;
+            } else {
+                const uint32_t f = (uint32_t)__builtin_ctzll(m);
+                const uint32_t nh = min(lo + f * step, hi);
+                lo = f ? lo + (f - 1) * step + 1 : lo;
+                hi = nh;
+            }
         }
-        split[tid] = lo;
+        if (lane == 0) split[tid >> 6] = lo;
     }
     __syncthreads();
     const uint32_t ia = a0 + split[0], la = split[1] - split[0];
