@@ -44,8 +44,13 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        build(force=False)
-        lib = ctypes.CDLL(_LIB)
+        # DSS_ORACLE_LIB: a deliberately broken build, used only by the mutation tests to show
+        # that the pins catch planted mistakes.
+        path = os.environ.get("DSS_ORACLE_LIB")
+        if not path:
+            build(force=False)
+            path = _LIB
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         lib.oracle_dss.argtypes = [ctypes.c_int, P, P, ctypes.c_uint64, ctypes.c_uint64,
                                    ctypes.c_uint64, P, P, ctypes.POINTER(_Trace)]
