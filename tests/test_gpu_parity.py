@@ -274,3 +274,58 @@ def test_2p27_u64_pairs_zipf(ds):
     assert (np.bincount(out_v, minlength=n) == 1).all()
     same = out_k[1:] == out_k[:-1]
     assert (out_v[1:][same] > out_v[:-1][same]).all()
+
+
+def test_2p27_u64_pairs_uniform(ds):
+    """2^27 (uint64 key, uint32 value = input index), uniform keys: stable sort by the same
+    properties as the Zipf case, plus equality with numpy's sort of the keys."""
+    n = 1 << 27
+    say("2^27 u64 pairs uniform")
+    keys = synth.uniform_u64(n, 11)
+    vals = synth.index_values(n)
+    out_k, out_v, geo, ws = gpu_sort(ds, keys, vals)
+    assert geo.levels == 2
+    assert (out_k == np.sort(keys)).all()
+    assert (keys[out_v] == out_k).all()
+    assert (np.bincount(out_v, minlength=n) == 1).all()
+    same = out_k[1:] == out_k[:-1]
+    assert (out_v[1:][same] > out_v[:-1][same]).all()
+
+
+def test_two_level_f32_specials_2p25(ds):
+    """Two levels on float32 keys with duplicates, signed zeros, infinities and NaNs of both
+    signs: bit-exact against the oracle's stable sort (IEEE totalOrder)."""
+    n = 1 << 25
+    say("2^25 f32 two levels")
+    x = synth.normal_f32_segments(np.array([n]), 14, dup_frac=0.01, zero_log2=8)
+    bits = x.view(np.uint32).copy()
+    pos = (synth.draws64(15, 4096) % np.uint64(n)).astype(np.int64)
+    bits[pos] = np.resize(np.array([0x7F800000, 0xFF800000, 0x7FC00000, 0xFFC00001,
+                                    0x80000000, 0x00000000], np.uint32), pos.size)
+    keys = bits.view(np.float32)
+    out, _, geo, _ = gpu_sort(ds, keys)
+    assert geo.levels == 2
+    want, _ = oracle.stable_sort(keys)
+    assert (out.view(np.uint32) == want.view(np.uint32)).all()
+
+
+def test_two_level_u32_pairs_duplicates_2p25(ds):
+    """Two levels, 2^25 pairs over 256 distinct keys (every bucket boundary falls inside a run
+    of equal keys): values bit-exact against the oracle's stable sort."""
+    n = 1 << 25
+    say("2^25 u32 pairs, 256 distinct keys")
+    keys = (synth.draws32(16, n) & np.uint32(0xFF)).astype(np.uint32)
+    vals = synth.index_values(n)
+    out_k, out_v, geo, _ = gpu_sort(ds, keys, vals)
+    assert geo.levels == 2
+    want_k, want_v = oracle.stable_sort(keys, vals)
+    assert (out_k == want_k).all() and (out_v == want_v).all()
+
+
+def test_two_level_u64_keys_2p26(ds):
+    n = 1 << 26
+    say("2^26 u64 keys two levels")
+    keys = synth.zipf_u64(n, 17)
+    out, _, geo, _ = gpu_sort(ds, keys)
+    assert geo.levels == 2
+    assert (out == np.sort(keys)).all()
