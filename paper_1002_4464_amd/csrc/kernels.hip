@@ -10,8 +10,13 @@
 //                         sorted sublist, write a_ij.
 //   k_scan_*              Step 7: bucket-major exclusive prefix sum of the m x s matrix
 //                         (column sums, scan of the column sums, update of every column).
-//   k_relocate            Step 8: move each piece A_ij to l_ij.
-//   k_tile<MODE_FINAL>    Step 9: sort each bucket B_j inside one workgroup.
+//   k_relocate            Step 8 of a first level that feeds a second one: move each piece
+//                         A_ij to l_ij.
+//   k_gather_bsort        Steps 8-9 fused: one workgroup per bucket gathers its pieces into LDS
+//                         and sorts them (one launch per bucket size class).
+//   k_tile<MODE_FINAL>    the whole input when it fits one workgroup.
+//   k_seg_prepare         set-up of a batch of independent sorts (segmented sort).
+//   k_pack                copies between requests' buffers and a batch's staging array.
 // For inputs where one level would need too many samples, Step 9 runs Algorithm 1 again on
 // every bucket (the buckets become the segments of a second level).
 //
@@ -22,14 +27,6 @@
 #include <stdint.h>
 
 #include "dsort_internal.h"
-
-// Kernel selection knobs (both choices are bit-identical; they differ only in speed).
-#ifndef DSORT_BUCKET_SORT
-#define DSORT_BUCKET_SORT 0  // Steps 8-9: 0 = gather + merge sort, 1 = gather + radix sort
-#endif
-#ifndef DSORT_RADIX_L2
-#define DSORT_RADIX_L2 0     // level-2 sublists: 0 = merge tile sort, 1 = radix tile sort
-#endif
 
 namespace dsort {
 namespace {
@@ -104,12 +101,6 @@ template <class T> __device__ __forceinline__ uint32_t pidx(uint32_t i) {
 }
 template <class T> constexpr uint32_t lds_elems(uint32_t cap) { return cap + (cap >> PadShift<T>::v); }
 
-// pidx of 32-bit item t*E + k for a blocked layout, split into a per-thread base plus a
-// compile-time offset (E a power of two: no pad boundary falls inside [tE, tE + min(E,32))).
-template <int E> __device__ __forceinline__ uint32_t pblk_base(uint32_t t) {
-    return t * E + ((t * E) >> 5);
-}
-template <int E> constexpr uint32_t pblk_off(int k) { return (uint32_t)(k + (k >> 5)); }
 
 // f32 <-> IEEE totalOrder image.
 __device__ __forceinline__ uint32_t f32_in(uint32_t b) {
@@ -351,7 +342,7 @@ __device__ __forceinline__ void block_sort(T *lds, uint32_t P) {
     __syncthreads();
 }
 
-// ------------------------------------------------------------------------------ block radix sort
+// ------------------------------------------------------------------------------ wave and block scans
 
 // Inclusive prefix sum over the 64 lanes of a wave with DPP moves: shifts by 1, 2, 4, 8 within
 // each row of 16 lanes, then row broadcasts of lane 15 (into rows 1, 3) and lane 31 (rows 2, 3).
@@ -362,18 +353,6 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);  // row_shr:8
     x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false); // row_bcast:15
     x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false); // row_bcast:31
-    return x;
-}
-
-__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x = min(x, (uint32_t)__shfl_xor(x, d, 64));
-    return x;
-}
-
-__device__ __forceinline__ uint32_t wave_max(uint32_t x) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x = max(x, (uint32_t)__shfl_xor(x, d, 64));
     return x;
 }
 
@@ -395,177 +374,6 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *wsum, 
     return wsum[w] + inc - x;
 }
 
-// Block-wide min and max of one value per thread.  red: LDS scratch of 34 words.
-__device__ __forceinline__ void block_minmax(uint32_t lo, uint32_t hi, uint32_t *red,
-                                             uint32_t &mn, uint32_t &mx) {
-    const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
-    lo = wave_min(lo);
-    hi = wave_max(hi);
-    if (lane == 0) {
-        red[w] = lo;
-        red[16 + w] = hi;
-    }
-    __syncthreads();
-    if (t == 0) {
-        uint32_t a = red[0], b = red[16];
-        for (uint32_t i = 1; i < nw; ++i) {
-            a = min(a, red[i]);
-            b = max(b, red[16 + i]);
-        }
-        red[32] = a;
-        red[33] = b;
-    }
-    __syncthreads();
-    mn = red[32];
-    mx = red[33];
-}
-
-constexpr uint32_t kRadixBits = 4;
-
-// Stable LSD radix sort (4-bit digits) of the E * blockDim 32-bit keys held in registers, thread
-// t holding positions tE .. tE+E-1, ordered over bits [0, nbits) (the caller subtracts the
-// block's minimum key first).  Each pass: every thread counts its digits in its own column of
-// two 16-bit counters per word (digit d in word d mod 8, half d / 8), a raking scan over
-// (word, thread) turns the counts into the position of every thread's first key of every digit,
-// and keys scatter to those positions in LDS and are read back blocked.  The counters live in
-// the key buffer itself (keys are in registers while counting), so the sort needs only sk
-// (lds_elems(E * blockDim) words; 8 * blockDim <= that) plus 17 words of wsum.  On return
-// sk[pidx(i)] holds the sorted keys (sv the values).  Requires E * blockDim <= 65535.
-template <int E, bool V, uint32_t BD>
-__device__ __forceinline__ void block_radix_sort(uint32_t (&key)[E], uint32_t (&val)[E], uint32_t *sk,
-                                 uint32_t *sv, uint32_t *wsum, uint32_t nbits) {
-    const uint32_t t = threadIdx.x;
-    const uint32_t pb = pblk_base<E>(t);
-    uint32_t *cnt = sk;
-    if (nbits == 0) {  // every key equal: the input order is the stable order
-#pragma unroll
-        for (int k = 0; k < E; ++k) {
-            sk[pb + pblk_off<E>(k)] = key[k];
-            if (V) sv[pb + pblk_off<E>(k)] = val[k];
-        }
-        __syncthreads();
-        return;
-    }
-    for (uint32_t sh = 0; sh < nbits; sh += kRadixBits) {
-#pragma unroll
-        for (int l = 0; l < 8; ++l) cnt[l * BD + t] = 0;
-        uint32_t r[E];
-#pragma unroll
-        for (int k = 0; k < E; ++k) {
-            // The counter updates form one sequential chain through LDS anyway; computing each
-            // address just before its update keeps E addresses from being live at once.
-            asm volatile("" : "+v"(key[k])::"memory");
-            const uint32_t a = __builtin_amdgcn_ubfe(key[k], sh, 3) * BD + t;
-            const uint32_t hs = __builtin_amdgcn_ubfe(key[k], sh + 3, 1) << 4;
-            const uint32_t old = cnt[a];
-            cnt[a] = old + (1u << hs);
-            r[k] = __builtin_amdgcn_ubfe(old, hs, 16);
-        }
-        __syncthreads();
-        uint32_t seg[8];
-        uint32_t sum = 0;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            seg[i] = cnt[8 * t + i];
-            sum += seg[i];
-        }
-        uint32_t total;
-        uint32_t run = block_excl_scan(sum, wsum, total);
-        const uint32_t hi_off = (total & 0xFFFFu) << 16;  // low-half digits precede high-half ones
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            cnt[8 * t + i] = run + hi_off;
-            run += seg[i];
-        }
-        __syncthreads();
-        // Recompute each key's counter address rather than keeping 2E values live across the
-        // scan: the empty asm hides that the keys are unchanged.
-#pragma unroll
-        for (int k = 0; k < E; ++k) asm volatile("" : "+v"(key[k]));
-#pragma unroll
-        for (int k = 0; k < E; ++k) {
-            const uint32_t a = __builtin_amdgcn_ubfe(key[k], sh, 3) * BD + t;
-            const uint32_t hs = __builtin_amdgcn_ubfe(key[k], sh + 3, 1) << 4;
-            r[k] += __builtin_amdgcn_ubfe(cnt[a], hs, 16);
-        }
-        __syncthreads();  // every counter read before the keys overwrite them
-#pragma unroll
-        for (int k = 0; k < E; ++k) {
-            sk[pidx<uint32_t>(r[k])] = key[k];
-            if (V) sv[pidx<uint32_t>(r[k])] = val[k];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < E; ++k) {
-            key[k] = sk[pb + pblk_off<E>(k)];
-            if (V) val[k] = sv[pb + pblk_off<E>(k)];
-        }
-        __syncthreads();  // every key read before the next pass zeroes counters over them
-    }
-}
-
-// Loads the block's staged keys sk[0, count) (padded index) into registers, blocked, as offsets
-// from the block's smallest real key, with pads (positions >= count) set to the largest real
-// key so they stay behind every real key in a stable sort; returns the key range.
-template <int E>
-__device__ __forceinline__ void load_blocked_with_range(const uint32_t *sk, uint32_t count,
-                                                        uint32_t (&key)[E], uint32_t *red,
-                                                        uint32_t &kmin, uint32_t &kmax) {
-    const uint32_t t = threadIdx.x;
-    const uint32_t pb = pblk_base<E>(t);
-    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
-#pragma unroll
-    for (int k = 0; k < E; ++k) {
-        const uint32_t i = t * E + k;
-        key[k] = sk[pb + pblk_off<E>(k)];
-        if (i < count) {
-            lo = min(lo, key[k]);
-            hi = max(hi, key[k]);
-        }
-    }
-    block_minmax(lo, hi, red, kmin, kmax);
-#pragma unroll
-    for (int k = 0; k < E; ++k) key[k] = (t * E + k >= count) ? kmax - kmin : key[k] - kmin;
-}
-
-__device__ __forceinline__ uint32_t range_bits(uint32_t kmin, uint32_t kmax) {
-    return kmax > kmin ? 32u - (uint32_t)__clz(kmax - kmin) : 0u;
-}
-
-// Steps 1-3 for 32-bit keys without values: one workgroup (1024 threads, 16 keys each) per
-// sublist of L <= 16384 items; the local sort is the block radix sort above.
-// Eight waves per SIMD (64 VGPRs) lets two 1024-thread workgroups share a CU; the compiler
-// spills a few dwords for it, which costs less than the lost occupancy.
-template <bool XIN, uint32_t BD>
-__global__ __launch_bounds__(BD) __attribute__((amdgpu_waves_per_eu(8))) void k_tile_radix(const uint32_t *src, uint32_t *dst,
-                                                   SegView sv, uint32_t L, uint32_t s,
-                                                   uint64_t *samples) {
-    constexpr int E = 16;
-    __shared__ uint32_t sk[lds_elems<uint32_t>(E * BD)];
-    __shared__ uint32_t wsum[17], red[34];
-    const uint32_t tid = threadIdx.x, bd = blockDim.x;
-    TileLoc loc;
-    if (!locate_tile(sv, L, blockIdx.x, loc)) return;
-    const uint32_t begin = loc.seg_begin + loc.i * L;
-    const uint32_t count = min(L, loc.seg_size - loc.i * L);
-    for (uint32_t i = tid; i < count; i += bd) {
-        uint32_t k = src[begin + i];
-        if (XIN) k = f32_in(k);
-        sk[pidx<uint32_t>(i)] = k;
-    }
-    __syncthreads();
-    uint32_t key[E], dummy[E];
-    uint32_t kmin, kmax;
-    load_blocked_with_range<E>(sk, count, key, red, kmin, kmax);
-    block_radix_sort<E, false, BD>(key, dummy, sk, nullptr, wsum, range_bits(kmin, kmax));
-    const uint32_t w = L / s;
-    for (uint32_t k = tid; k < s; k += bd) {
-        const uint32_t r = (k + 1) * w - 1;
-        const uint32_t kr = r < count ? sk[pidx<uint32_t>(r)] + kmin : 0xFFFFFFFFu;  // pads
-        samples[(size_t)(loc.tile0 + loc.i) * s + k] = ((uint64_t)kr << 32) | (loc.i * L + r);
-    }
-    for (uint32_t i = tid; i < count; i += bd) dst[begin + i] = sk[pidx<uint32_t>(i)] + kmin;
-}
 
 // ------------------------------------------------------------------------------ Steps 1-3, 9
 
@@ -1089,58 +897,6 @@ __global__ __launch_bounds__(256) void k_relocate(const K *src, K *dst, const ui
 
 // ------------------------------------------------------------------------------ Steps 8+9
 
-// Merges nr sorted runs lds[bnd[r], bnd[r+1]) (bnd: LDS, bnd[0] = 0, bnd[nr] = total,
-// non-decreasing; empty runs allowed) pairwise, level by level, into one sorted run; earlier
-// runs win ties, so the merge is stable.  At each level every pair of runs is cut into chunks of
-// E outputs (the last one partial), so no chunk straddles two pairs; chunk q goes to slot
-// q = c * blockDim + thread (c < CH).  Requires total / E + ceil(nr / 2) <= CH * blockDim.
-// cp: LDS scratch of at least ceil(nr / 2) + 1 entries.
-template <class T, int E, int CH>
-__device__ __forceinline__ void block_merge_runs(T *lds, const uint32_t *bnd, uint32_t *cp, uint32_t nr,
-                                 uint32_t total) {
-    const uint32_t t = threadIdx.x, bd = blockDim.x;
-    const uint32_t lim = total - 1;
-    T x[CH][E];
-    uint32_t xo[CH], xc[CH];
-    for (uint32_t S = 1; S < nr; S <<= 1) {
-        const uint32_t S2 = 2 * S;
-        const uint32_t npairs = (nr + S2 - 1) / S2;
-        for (uint32_t p = t; p < npairs; p += bd) {
-            const uint32_t st = bnd[min(p * S2, nr)], en = bnd[min(p * S2 + S2, nr)];
-            cp[p] = (en - st + E - 1) / E;
-        }
-        const uint32_t nchunks = lds_scan(cp, npairs);
-#pragma unroll
-        for (int c = 0; c < CH; ++c) {
-            const uint32_t q = c * bd + t;
-            xc[c] = 0;
-            if (q < nchunks) {
-                uint32_t lo = 0, hi = npairs - 1;  // pair of chunk q: largest p with cp[p] <= q
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi + 1) >> 1;
-                    if (cp[mid] <= q) lo = mid; else hi = mid - 1;
-                }
-                const uint32_t p = lo;
-                const uint32_t a0 = bnd[min(p * S2, nr)];
-                const uint32_t a1 = bnd[min(p * S2 + S, nr)];
-                const uint32_t b1 = bnd[min(p * S2 + S2, nr)];
-                const uint32_t diag = (q - cp[p]) * E;
-                const uint32_t k = merge_path<T>(lds, a0, a1 - a0, a1, b1 - a1, diag);
-                serial_merge<T, E>(lds, a0 + k, a1, a1 + diag - k, b1, lim, x[c]);
-                xo[c] = a0 + diag;
-                xc[c] = min((uint32_t)E, b1 - xo[c]);
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < CH; ++c) {
-#pragma unroll
-            for (int e = 0; e < E; ++e)
-                if ((uint32_t)e < xc[c]) lds[pidx<T>(xo[c] + e)] = x[c][e];
-        }
-        __syncthreads();
-    }
-}
 
 struct GatherArgs {
     const void *src_keys;    // sorted sublists of the last level
@@ -1174,194 +930,7 @@ template <class K, bool V, int CAP> struct GatherE {
     static constexpr int wpe = V ? DSORT_PAIR_GATHER_WPE : 1;
     static_assert((E & (E - 1)) == 0 && CAP % E == 0 && CAP / E <= 1024, "bucket class shape");
 };
-constexpr int kGatherE = 16;
 
-// Threads and chunks per thread of the class holding CAP items: enough chunk slots for
-// CAP / E chunks plus one partial chunk per pair of pieces (at most kMaxPieces / 2).
-template <int CAP> struct GatherShape {
-    static constexpr uint32_t need = CAP / kGatherE + kMaxPieces / 2;
-    static constexpr int CH = need <= 1024 ? 1 : (need <= 2048 ? 2 : 3);
-    static constexpr uint32_t BD = ((need + CH - 1) / CH + 63) / 64 * 64;
-    static_assert(BD <= 1024, "class too large for one workgroup");
-};
-
-// Steps 8 and 9 fused, one workgroup per bucket B_j of one size class (persistent: each
-// workgroup walks the class's work list).  Every piece A_ij is read from its sorted sublist
-// straight into LDS at its place l_ij in the bucket (the relocation of Step 8, staged in LDS),
-// then the m sorted pieces are merged into the sorted bucket (Step 9) and written out.
-template <class K, bool V, int CAP, bool XOUT>
-__global__ __launch_bounds__(GatherShape<CAP>::BD) void k_gather_merge(GatherArgs a,
-                                                                     uint32_t cls) {
-    using R = Tr<K, V>;
-    using T = typename R::T;
-    constexpr int E = kGatherE;
-    constexpr uint32_t BD = GatherShape<CAP>::BD;
-    constexpr int CH = GatherShape<CAP>::CH;
-    __shared__ T lds[lds_elems<T>(CAP)];
-    __shared__ uint32_t bnd[kMaxPieces + 1], ps[kMaxPieces], cp[kMaxPieces / 2 + 1];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = tid & 63, w = tid >> 6, nw = BD >> 6;
-    const uint32_t nwork = min(a.count[cls], a.stride);
-    const uint32_t *list = a.list + (size_t)cls * a.stride;
-    const K *src = (const K *)a.src_keys;
-    K *dst = (K *)a.dst_keys;
-    for (uint32_t item = blockIdx.x; item < nwork; item += gridDim.x) {
-        const uint4 b = a.buckets[list[item]];
-        const uint32_t begin = b.x, total = b.y, pbase = b.z, np = b.w;
-        if (total == 0 || total > CAP || np > kMaxPieces || np == 0 ||
-            (uint64_t)begin + total > a.n_total) {
-            if (tid == 0) atomicOr(a.status, 8u);
-            continue;
-        }
-        __syncthreads();  // the previous bucket is done with the LDS tables
-        for (uint32_t i = tid; i < np; i += BD) {
-            bnd[i] = min(a.pdst[pbase + i] - begin, total);
-            ps[i] = a.psrc[pbase + i];
-        }
-        if (tid == 0) bnd[np] = total;
-        __syncthreads();
-        // Gather: wave w streams its slice of the bucket 64 consecutive items at a time, each
-        // lane following the piece its item falls in.
-        const uint32_t span = ((total + nw - 1) / nw + 63) & ~63u;
-        const uint32_t x_begin = w * span, x_end = min(total, x_begin + span);
-        if (x_begin < x_end) {
-            uint32_t p = 0;
-            {
-                uint32_t lo = 0, hi = np - 1;  // largest p with bnd[p] <= x
-                const uint32_t xs = min(x_begin + lane, total - 1);
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi + 1) >> 1;
-                    if (bnd[mid] <= xs) lo = mid; else hi = mid - 1;
-                }
-                p = lo;
-            }
-            for (uint32_t row = x_begin; row < x_end; row += 4 * 64) {
-                K v[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint32_t xu = row + 64 * u + lane;
-                    if (xu < x_end) {
-                        while (xu >= bnd[p + 1]) ++p;
-                        v[u] = src[ps[p] + (xu - bnd[p])];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint32_t xu = row + 64 * u + lane;
-                    if (xu < x_end) lds[pidx<T>(xu)] = R::make(v[u], xu);
-                }
-            }
-        }
-        __syncthreads();
-        block_merge_runs<T, E, CH>(lds, bnd, cp, np, total);
-
-        uint32_t pos[CH][E];
-#pragma unroll
-        for (int c = 0; c < CH; ++c) {
-            const uint32_t x0 = (c * BD + tid) * E;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const uint32_t x = x0 + e;
-                if (x < total) {
-                    const T el = lds[pidx<T>(x)];
-                    K kk = R::key(el);
-                    if (XOUT) kk = (K)f32_out((uint32_t)kk);
-                    dst[begin + x] = kk;
-                    pos[c][e] = R::lpos(el);
-                }
-            }
-        }
-        if (V) {
-            __syncthreads();
-            uint32_t *lv = (uint32_t *)lds;
-            for (uint32_t i = w; i < np; i += nw) {
-                const uint32_t d0 = bnd[i], len = bnd[i + 1] - d0, s0 = ps[i];
-                for (uint32_t q = lane; q < len; q += 64) lv[d0 + q] = a.src_vals[s0 + q];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const uint32_t x0 = (c * BD + tid) * E;
-#pragma unroll
-                for (int e = 0; e < E; ++e)
-                    if (x0 + e < total) a.dst_vals[begin + x0 + e] = lv[pos[c][e]];
-            }
-        }
-    }
-}
-
-// Steps 8 and 9 fused for 32-bit keys without values, buckets of at most CAP = 16 * BD
-// items: the pieces are gathered into LDS as above, then the bucket is sorted with the block
-// radix sort over the key range it actually holds.
-template <int CAP, bool XOUT>
-__global__ __launch_bounds__(CAP / 16) __attribute__((amdgpu_waves_per_eu(8))) void k_gather_radix(GatherArgs a, uint32_t cls) {
-    constexpr int E = 16;
-    constexpr uint32_t BD = CAP / E;
-    __shared__ uint32_t sk[lds_elems<uint32_t>(CAP)];
-    __shared__ uint32_t bnd[kMaxPieces + 1], ps[kMaxPieces], wsum[17], red[34];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = tid & 63, w = tid >> 6, nw = BD >> 6;
-    const uint32_t nwork = min(a.count[cls], a.stride);
-    const uint32_t *list = a.list + (size_t)cls * a.stride;
-    const uint32_t *src = (const uint32_t *)a.src_keys;
-    uint32_t *dst = (uint32_t *)a.dst_keys;
-    for (uint32_t item = blockIdx.x; item < nwork; item += gridDim.x) {
-        const uint4 b = a.buckets[list[item]];
-        const uint32_t begin = b.x, total = b.y, pbase = b.z, np = b.w;
-        if (total == 0 || total > CAP || np > kMaxPieces || np == 0 ||
-            (uint64_t)begin + total > a.n_total) {
-            if (tid == 0) atomicOr(a.status, 8u);
-            continue;
-        }
-        __syncthreads();
-        for (uint32_t i = tid; i < np; i += BD) {
-            bnd[i] = min(a.pdst[pbase + i] - begin, total);
-            ps[i] = a.psrc[pbase + i];
-        }
-        if (tid == 0) bnd[np] = total;
-        __syncthreads();
-        const uint32_t span = ((total + nw - 1) / nw + 63) & ~63u;
-        const uint32_t x_begin = w * span, x_end = min(total, x_begin + span);
-        if (x_begin < x_end) {
-            uint32_t p = 0;
-            {
-                uint32_t lo = 0, hi = np - 1;
-                const uint32_t xs = min(x_begin + lane, total - 1);
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi + 1) >> 1;
-                    if (bnd[mid] <= xs) lo = mid; else hi = mid - 1;
-                }
-                p = lo;
-            }
-            for (uint32_t row = x_begin; row < x_end; row += 4 * 64) {
-                uint32_t v[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint32_t xu = row + 64 * u + lane;
-                    if (xu < x_end) {
-                        while (xu >= bnd[p + 1]) ++p;
-                        v[u] = src[ps[p] + (xu - bnd[p])];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint32_t xu = row + 64 * u + lane;
-                    if (xu < x_end) sk[pidx<uint32_t>(xu)] = v[u];
-                }
-            }
-        }
-        __syncthreads();
-        uint32_t key[E], dummy[E];
-        uint32_t kmin, kmax;
-        load_blocked_with_range<E>(sk, total, key, red, kmin, kmax);
-        block_radix_sort<E, false, BD>(key, dummy, sk, nullptr, wsum, range_bits(kmin, kmax));
-        for (uint32_t i = tid; i < total; i += BD) {
-            uint32_t kk = sk[pidx<uint32_t>(i)] + kmin;
-            if (XOUT) kk = f32_out(kk);
-            dst[begin + i] = kk;
-        }
-    }
-}
 
 // Steps 8 and 9 fused, merge-sort flavour: the pieces of a bucket are gathered into LDS as
 // above (with their bucket positions as tie-breaks for key/value sorts), padded with key-max
@@ -1637,12 +1206,6 @@ template <class K, bool V, bool F32> struct Pipeline {
     static constexpr int SCAP = SE * 1024;
     using T = typename R::T;
     using CC = ClassCaps<T>;
-    // 32-bit keys without values use the radix local sorts; other layouts the merge sorts.
-    static constexpr bool kRadix = !V && sizeof(K) == 4;
-    static constexpr bool kRadixLevel1 = false;
-    static constexpr bool kRadixLevel2 = DSORT_RADIX_L2 != 0;
-    // Steps 8-9: gather + block merge sort (default), or the radix / run-merge kernels.
-    static constexpr bool kBucketMerge = DSORT_BUCKET_SORT == 0;
     static_assert(CC::cap[CC::n - 1] == (uint32_t)FCAP, "last class must be the bucket capacity");
 
     static Classes classes(uint32_t *status, uint32_t *lists, uint32_t stride) {
@@ -1655,41 +1218,21 @@ template <class K, bool V, bool F32> struct Pipeline {
         return c;
     }
 
-    // One persistent launch per size class, each sized to fill the chip at its occupancy.
+    // One persistent launch per size class, each sized to fill the chip at its occupancy
+    // (the smaller of what LDS and the wave slots allow per CU).
     template <uint32_t I, bool XIN = false>
     static int gather_classes(const GatherArgs &a, hipStream_t st, Timing *tm) {
-        static_assert(!XIN || kBucketMerge, "f32 input on the gather needs the merge kernel");
         if constexpr (I < CC::n) {
             constexpr int CAP = (int)CC::cap[I];
-            if constexpr (kBucketMerge) {
-                constexpr int GE = GatherE<K, V, CAP>::E;
-                constexpr uint32_t GBD = CAP / GE;
-                constexpr uint32_t glds = (lds_elems<T>(CAP) + 1) * sizeof(T) + 8 * (kMaxPieces + 1);
-                constexpr uint32_t gby_lds = 163840u / glds;
-                constexpr uint32_t gby_waves = 32u / ((GBD + 63) / 64);
-                constexpr uint32_t gocc = gby_lds < gby_waves ? gby_lds : gby_waves;
-                const uint32_t grid = min(a.stride, kNumCUs * (gocc ? gocc : 1u));
-                DS_LAUNCH("s89_gather_sort", (k_gather_bsort<K, V, CAP, F32, XIN>), dim3(grid),
-                          dim3(GBD), a, I);
-            } else if constexpr (kRadix && CAP <= 16384) {
-                constexpr uint32_t RBD = CAP / 16;
-                constexpr uint32_t rlds = lds_elems<uint32_t>(CAP) * 4 + 8 * (kMaxPieces + 1) + 256;
-                constexpr uint32_t rby_lds = 163840u / rlds;
-                constexpr uint32_t rby_waves = 32u / (RBD / 64);
-                constexpr uint32_t rocc = rby_lds < rby_waves ? rby_lds : rby_waves;
-                const uint32_t grid = min(a.stride, kNumCUs * (rocc ? rocc : 1u));
-                DS_LAUNCH("s89_gather_sort", (k_gather_radix<CAP, F32>), dim3(grid), dim3(RBD), a,
-                          I);
-            } else {
-                constexpr uint32_t BD = GatherShape<CAP>::BD;
-                constexpr uint32_t lds = lds_elems<T>(CAP) * sizeof(T) + 8 * (kMaxPieces + 1);
-                constexpr uint32_t by_lds = 163840u / lds;
-                constexpr uint32_t by_waves = 32u / (BD / 64);
-                constexpr uint32_t occ = by_lds < by_waves ? by_lds : by_waves;
-                const uint32_t grid = min(a.stride, kNumCUs * (occ ? occ : 1u));
-                DS_LAUNCH("s89_gather_merge", (k_gather_merge<K, V, CAP, F32>), dim3(grid),
-                          dim3(BD), a, I);
-            }
+            constexpr int GE = GatherE<K, V, CAP>::E;
+            constexpr uint32_t GBD = CAP / GE;
+            constexpr uint32_t glds = (lds_elems<T>(CAP) + 1) * sizeof(T) + 8 * (kMaxPieces + 1);
+            constexpr uint32_t gby_lds = 163840u / glds;
+            constexpr uint32_t gby_waves = 32u / ((GBD + 63) / 64);
+            constexpr uint32_t gocc = gby_lds < gby_waves ? gby_lds : gby_waves;
+            const uint32_t grid = min(a.stride, kNumCUs * (gocc ? gocc : 1u));
+            DS_LAUNCH("s89_gather_sort", (k_gather_bsort<K, V, CAP, F32, XIN>), dim3(grid),
+                      dim3(GBD), a, I);
             return gather_classes<I + 1, XIN>(a, st, tm);
         }
         return DSORT_OK;
@@ -1717,22 +1260,6 @@ template <class K, bool V, bool F32> struct Pipeline {
             SC *t = x;
             x = y;
             y = t;
-        }
-        return DSORT_OK;
-    }
-
-    // Steps 1-3 with the radix tile kernel instantiated for the sublist length.
-    template <bool XIN>
-    static int tile_radix(const char *name, uint32_t L, uint32_t grid, const uint32_t *src,
-                          uint32_t *dst, SegView sv, uint32_t s, uint64_t *samples,
-                          hipStream_t st, Timing *tm) {
-        switch (L) {
-            case 1024: DS_LAUNCH(name, (k_tile_radix<XIN, 64>), dim3(grid), dim3(64), src, dst, sv, L, s, samples); break;
-            case 2048: DS_LAUNCH(name, (k_tile_radix<XIN, 128>), dim3(grid), dim3(128), src, dst, sv, L, s, samples); break;
-            case 4096: DS_LAUNCH(name, (k_tile_radix<XIN, 256>), dim3(grid), dim3(256), src, dst, sv, L, s, samples); break;
-            case 8192: DS_LAUNCH(name, (k_tile_radix<XIN, 512>), dim3(grid), dim3(512), src, dst, sv, L, s, samples); break;
-            case 16384: DS_LAUNCH(name, (k_tile_radix<XIN, 1024>), dim3(grid), dim3(1024), src, dst, sv, L, s, samples); break;
-            default: return DSORT_E_UNSUPPORTED;
         }
         return DSORT_OK;
     }
@@ -1846,14 +1373,8 @@ template <class K, bool V, bool F32> struct Pipeline {
         K *tiles = g.levels == 1 ? wkeys : keys;
         uint32_t *tvals = g.levels == 1 ? wvals : d_vals;
 
-        // Steps 1-3.  Full-range 32-bit sublists sort faster with the merge tile kernel (about
-        // 260 VALU instructions per key at full VALU issue) than with eight radix passes; the
-        // radix kernel serves sublists of one bucket, whose narrower key range needs fewer passes.
-        if (kRadix && kRadixLevel1 && g.L1 >= 1024) {
-            int rc0 = tile_radix<F32>("s123_local_sort", g.L1, g.m1, (const uint32_t *)keys,
-                                      (uint32_t *)tiles, sv1, g.s1, (uint64_t *)samp, st, tm);
-            if (rc0) return rc0;
-        } else {
+        // Steps 1-3
+        {
             TileArgs a{keys, tiles, d_vals, tvals, sv1, g.L1, g.s1, samp, status};
             DS_LAUNCH("s123_local_sort", (k_tile<K, V, TE, TCAP, MODE_SAMPLE, F32, false>),
                       dim3(g.m1), dim3(g.L1 / TE), a);
@@ -1898,12 +1419,7 @@ template <class K, bool V, bool F32> struct Pipeline {
         uint32_t *pdst2 = (uint32_t *)(ws + g.o_pdst2);
         uint32_t *psrc2 = (uint32_t *)(ws + g.o_psrc2);
         uint4 *finals = (uint4 *)(ws + g.o_final);
-        if (kRadix && kRadixLevel2 && g.L2 >= 1024) {
-            int rc0 = tile_radix<false>("l2_s123_local_sort", g.L2, g.tiles2max,
-                                        (const uint32_t *)wkeys, (uint32_t *)wkeys, sv2, g.s2,
-                                        (uint64_t *)samp2, st, tm);
-            if (rc0) return rc0;
-        } else {
+        {
             TileArgs a{wkeys, wkeys, wvals, wvals, sv2, g.L2, g.s2, samp2, status};
             DS_LAUNCH("l2_s123_local_sort", (k_tile<K, V, TE, TCAP, MODE_SAMPLE, false, false>),
                       dim3(g.tiles2max), dim3(g.L2 / TE), a);
