@@ -67,8 +67,10 @@ typedef struct dsort_plan_s *dsort_plan_t;
  * On success *out receives the plan (host memory, owned by the caller until
  * dsort_plan_destroy) and *workspace_bytes the size of the device workspace every call
  * with this plan needs.  The plan holds host state only and allocates no device memory.
- * Errors: DSORT_E_INVALID (NULL out/workspace_bytes, bad type, max_items above the limit
- * 2^32 - 2^16), DSORT_E_UNSUPPORTED (tuning cannot be realised), DSORT_E_NOMEM. */
+ * Errors: DSORT_E_INVALID (NULL out/workspace_bytes, bad type, max_items above 2^32 - 2^16),
+ * DSORT_E_UNSUPPORTED (the tuning cannot be realised, or max_items is beyond what two levels
+ * of Algorithm 1 reach: 1,108,377,600 items for 32-bit keys, 554,188,800 for 32-bit keys with
+ * values and for 64-bit keys, 286,326,784 for 64-bit keys with values), DSORT_E_NOMEM. */
 int dsort_plan(dsort_plan_t *out, int key_type, int with_values, uint64_t max_items,
                uint64_t max_segments, const dsort_tuning_t *tuning, size_t *workspace_bytes);
 

@@ -250,3 +250,18 @@ def test_server_rejects_bad_arguments_without_gpu():
     st = ds._ServerStats()
     assert lib.dsort_server_stats(None, ctypes.byref(st)) == ds.E_INVALID
     assert lib.dsort_server_destroy(None) == ds.OK
+
+
+def test_largest_plannable_sizes():
+    """Two levels of Algorithm 1 reach about 2^30 32-bit keys (less for wider items); a plan
+    for more is refused up front (DSORT_E_UNSUPPORTED), never at sort time."""
+    def ok(kt, v, n):
+        try:
+            ds.Plan(kt, v, n)
+            return True
+        except ds.DsortError as e:
+            assert e.status == ds.E_UNSUPPORTED
+            return False
+    for kt, v, limit in [(1, False, 1108377600), (3, False, 1108377600), (1, True, 554188800),
+                         (2, False, 554188800), (2, True, 286326784)]:
+        assert ok(kt, v, limit) and not ok(kt, v, limit + 1)

@@ -329,3 +329,58 @@ def test_two_level_u64_keys_2p26(ds):
     out, _, geo, _ = gpu_sort(ds, keys)
     assert geo.levels == 2
     assert (out == np.sort(keys)).all()
+
+
+def _largest_plannable(ds, kt, values):
+    lo, hi = 1 << 20, (1 << 32) - (1 << 16)
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        try:
+            ds.Plan(kt, values, mid)
+            lo = mid
+        except ds.DsortError:
+            hi = mid - 1
+    return lo
+
+
+@pytest.mark.timeout(900)
+def test_largest_u32_sort(ds):
+    """The largest uint32 sort a plan accepts (about 1.1e9 keys, 4.4 GB): output
+    non-decreasing and the multiset unchanged (two 64-bit hashes summed over the array),
+    checked on the device in chunks."""
+    import torch
+    n = _largest_plannable(ds, 1, False)
+    say("largest u32 sort n =", n)
+    assert n > 1 << 30
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2024)
+    keys = torch.empty(n, dtype=torch.int32, device="cuda")
+    chunk = 1 << 27
+
+    def image(c):
+        return c.to(torch.int64) & 0xFFFFFFFF
+
+    def hashes():
+        h1 = torch.zeros((), dtype=torch.int64, device="cuda")
+        h2 = torch.zeros((), dtype=torch.int64, device="cuda")
+        for a in range(0, n, chunk):
+            x = image(keys[a:a + chunk])
+            h1 += ((x * 0x9E3779B97F4A7C15 + 0x632BE59BD9B4E019) ^ (x >> 7)).sum()
+            h2 += ((x ^ 0x5851F42D4C957F2D) * 0x2545F4914F6CDD1D).sum()
+        return int(h1), int(h2)
+
+    for a in range(0, n, chunk):
+        m = min(chunk, n - a)
+        keys[a:a + m] = torch.randint(-(1 << 31), 1 << 31, (m,), dtype=torch.int64,
+                                      device="cuda", generator=gen).to(torch.int32)
+    before = hashes()
+    plan = ds.Plan(1, False, n)
+    ws = plan.workspace("cuda")
+    plan.sort_keys(keys, ws)
+    torch.cuda.synchronize()
+    geo = plan.geometry(n)
+    assert int(ws_view(ws, geo.off_status, 1, np.uint32)[0]) == 0
+    for a in range(0, n, chunk):
+        x = image(keys[a:min(n, a + chunk + 1)])
+        assert bool((x[1:] >= x[:-1]).all()), f"order broken near {a}"
+    assert hashes() == before
