@@ -95,17 +95,120 @@ def traffic_for(stage: str):
     return float(v) if v is not None else None
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(seed: int, sample_log2: int, L: int, s: int):
+    """The single-threaded C oracle of Algorithm 1, pinned to one host core, on the first
+    2^sample_log2 keys of the benchmark's stream."""
     import oracle
     n = 1 << sample_log2
     keys = __import__("synth").uniform_u32(n, seed)
-    t0 = time.perf_counter()
-    out, _, _ = oracle.dss(keys, L, s)
-    dt = time.perf_counter() - t0
+    oracle.build(force=False)
+    old = os.sched_getaffinity(0)
+    core = min(old)
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        out, _, _ = oracle.dss(keys, L, s)
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, old)
     assert (out[1:] >= out[:-1]).all()
     return {"value": round(n / dt / 1e6, 3), "unit": "Mkeys/s", "cores": 1, "kind": "oracle",
+            "cpu": cpu_model(), "host_cpus": len(old),
             "sample": f"first 2^{sample_log2} keys of the same uniform stream (seed {seed}); "
-                      f"single-threaded C oracle of Algorithm 1 with L={L}, s={s}; {dt:.1f} s"}
+                      f"single-threaded C oracle of Algorithm 1 with L={L}, s={s}, pinned to "
+                      f"core {core}; {dt:.1f} s"}
+
+
+def path_roofline(n: int, kb: int, ms: float) -> dict:
+    """Whole-sort HBM fractions: measured bytes of all passes (rocprofv3 counters recorded for
+    this kernel source) over the sort time, and the one-level algorithmic floor of 7 n b bytes
+    (Steps 2, 8 and 9 read and write the data, Step 6 reads it once)."""
+    rec = {"floor_7nb_gbs": round(7 * n * kb / (ms * 1e-3) / 1e9, 1)}
+    rec["floor_frac"] = round(rec["floor_7nb_gbs"] / HBM_PEAK_GBS, 4)
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        if t.get("kernel_source_sha256_16") == kernel_hash():
+            tot = sum(t["bytes_per_step"].values())
+            rec["measured_bytes"] = round(tot)
+            rec["measured_gbs"] = round(tot / (ms * 1e-3) / 1e9, 1)
+            rec["measured_frac"] = round(rec["measured_gbs"] / HBM_PEAK_GBS, 4)
+    except (OSError, KeyError, ValueError):
+        pass
+    return rec
+
+
+def sweep(args, ds, torch, dev):
+    """Mkeys/s against n for each layout (the paper's constant-rate experiment), and time
+    against the samples per sublist s at fixed n (its s experiment), at this GPU's sizes."""
+    import synth
+    out = {"n_sweep": [], "s_sweep": []}
+
+    def timed(plan, k, v, reps=5):
+        ws = plan.workspace(dev)
+        bufs = [k.clone() for _ in range(reps + 1)]
+        vb = [v.clone() for _ in range(reps + 1)] if v is not None else None
+        st = torch.cuda.current_stream(dev)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        for i in range(reps + 1):
+            if i == 1:
+                ev[0].record(st)
+            if vb is None:
+                plan.sort_keys(bufs[i], ws, st)
+            else:
+                plan.sort_pairs(bufs[i], vb[i], ws, st)
+            if i >= 1:
+                ev[i].record(st)
+        torch.cuda.synchronize()
+        ms = sorted(ev[i - 1].elapsed_time(ev[i]) for i in range(1, reps + 1))
+        return ms[len(ms) // 2]
+
+    layouts = [("u32", ds.U32, False, 28), ("u32 pairs", ds.U32, True, 27),
+               ("u64", ds.U64, False, 27), ("u64 pairs", ds.U64, True, 27)]
+    for name, kt, vals, top in layouts:
+        for lg in range(16, top + 1, 2 if top % 2 == 0 else 1):
+            n = 1 << lg
+            if kt == ds.U64:
+                k = torch.from_numpy(synth.uniform_u64(n, 9).view(np.int64)).to(dev)
+            else:
+                k = torch.from_numpy(synth.uniform_u32(n, 2).view(np.int32)).to(dev)
+            v = torch.arange(n, dtype=torch.int32, device=dev) if vals else None
+            plan = ds.Plan(kt, vals, n)
+            ms = timed(plan, k, v)
+            g = plan.geometry(n)
+            out["n_sweep"].append({"layout": name, "n": n, "ms": round(ms, 4),
+                                   "mkeys_s": round(n / ms / 1e3, 1), "levels": g.levels})
+            log(f"[bench] sweep {name} 2^{lg}: {ms:.3f} ms")
+            del k, v, plan
+            torch.cuda.empty_cache()
+    for lg in (25, 26, 27):
+        n = 1 << lg
+        k = torch.from_numpy(synth.uniform_u32(n, 2).view(np.int32)).to(dev)
+        for s in (16, 32, 64, 128, 256, 512, 1024):
+            try:
+                plan = ds.Plan(ds.U32, False, n, ds.Tuning(16384, s, 0, 0, 2))
+            except ds.DsortError:
+                continue
+            ms = timed(plan, k, None)
+            g = plan.geometry(n)
+            out["s_sweep"].append({"n": n, "s": s, "s2": g.samples2, "ms": round(ms, 4),
+                                   "mkeys_s": round(n / ms / 1e3, 1)})
+            log(f"[bench] s sweep 2^{lg} s={s}: {ms:.3f} ms")
+            del plan
+            torch.cuda.empty_cache()
+        del k
+    return out
 
 
 def batched_leg(args, ds, torch, dev):
@@ -132,14 +235,12 @@ def batched_leg(args, ds, torch, dev):
     for i in range(W):
         plan.sort_segmented(bufs[i], t_off, max_segment=max_seg, workspace=ws, stream=stream)
     torch.cuda.synchronize()
-    plan.set_timing(True)
     log(f"[bench] batched: timing {K} segmented calls")
     t0 = time.perf_counter()
     for i in range(W, W + K):
         plan.sort_segmented(bufs[i], t_off, max_segment=max_seg, workspace=ws, stream=stream)
     torch.cuda.synchronize()
     dt_default = (time.perf_counter() - t0) / K
-    plan.set_timing(False)
     # autotune (L, s) per length class on the pristine batch, then time again
     log("[bench] batched: autotuning")
     t0 = time.perf_counter()
@@ -153,13 +254,20 @@ def batched_leg(args, ds, torch, dev):
     for i in range(W):
         plan.sort_segmented(bufs[i], t_off, max_segment=max_seg, workspace=ws, stream=stream)
     torch.cuda.synchronize()
-    plan.set_timing(True)
     log(f"[bench] batched: timing {K} tuned segmented calls")
     t0 = time.perf_counter()
     for i in range(W, W + K):
         plan.sort_segmented(bufs[i], t_off, max_segment=max_seg, workspace=ws, stream=stream)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / K
+    # per-kernel times on K more calls with the library's HIP events switched on
+    for b in bufs[W:]:
+        b.copy_(src)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    for i in range(W, W + K):
+        plan.sort_segmented(bufs[i], t_off, max_segment=max_seg, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
     stages = plan.stage_times()
     plan.set_timing(False)
     status = int(ws[:4].cpu().numpy().view(np.uint32)[0])
@@ -294,13 +402,18 @@ def served_leg(args, ds, torch, dev):
     span_sat, lat_sat = run(np.zeros(R))
     for (wk, wv), (rk, rv) in zip(work, ref):
         assert torch.equal(wk, rk) and (wv is None or torch.equal(wv, rv)), "served != plain"
-    rate = args.served_load * R / t_b2b  # requests per second
     u = (synth.draws64(args.served_seed + 1, R) >> np.uint64(11)).astype(np.float64) / 2.0**53
-    gaps = -np.log(1.0 - u) / rate
-    log(f"[bench] served: Poisson run at {args.served_load:.2f} x back-to-back capacity")
-    span_p, lat_p = run(gaps)
-    for (wk, wv), (rk, rv) in zip(work, ref):
-        assert torch.equal(wk, rk) and (wv is None or torch.equal(wv, rv)), "served != plain"
+    poisson = []
+    for load in args.served_loads:
+        rate = load * R / t_b2b  # requests per second
+        gaps = -np.log(1.0 - u) / rate
+        log(f"[bench] served: Poisson run at {load:.2f} x back-to-back capacity")
+        span_p, lat_p = run(gaps)
+        for (wk, wv), (rk, rv) in zip(work, ref):
+            assert torch.equal(wk, rk) and (wv is None or torch.equal(wv, rv)), "served != plain"
+        poisson.append({"offered_load": load, "mkeys_s": round(total / span_p / 1e6, 1),
+                        "p50_ms": round(float(np.percentile(lat_p, 50)) * 1e3, 3),
+                        "p99_ms": round(float(np.percentile(lat_p, 99)) * 1e3, 3)})
     st = srv.stats()
     srv.close()
     del pristine, work, ref
@@ -316,10 +429,11 @@ def served_leg(args, ds, torch, dev):
         "saturated_speedup_vs_back_to_back": round(t_b2b / span_sat, 3),
         "saturated_p50_ms": round(float(np.percentile(lat_sat, 50)) * 1e3, 3),
         "saturated_p99_ms": round(float(np.percentile(lat_sat, 99)) * 1e3, 3),
-        "offered_load": args.served_load,
-        "poisson_mkeys_s": round(total / span_p / 1e6, 1),
-        "poisson_p50_ms": round(float(np.percentile(lat_p, 50)) * 1e3, 3),
-        "poisson_p99_ms": round(float(np.percentile(lat_p, 99)) * 1e3, 3),
+        "offered_load": poisson[0]["offered_load"],
+        "poisson_mkeys_s": poisson[0]["mkeys_s"],
+        "poisson_p50_ms": poisson[0]["p50_ms"],
+        "poisson_p99_ms": poisson[0]["p99_ms"],
+        "poisson_runs": poisson,
         "units": st["units"], "batched_units": st["batched_units"],
         "batched_requests": st["batched_requests"], "max_batch": st["max_batch"],
         "peak_arena_gib": round(st["peak_arena_bytes"] / 2**30, 3),
@@ -421,11 +535,12 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--batched-plain-steps", type=int, default=2)
     ap.add_argument("--no-served", action="store_true", help="skip the served leg")
-    ap.add_argument("--only", choices=["batched", "served"],
+    ap.add_argument("--only", choices=["batched", "served", "sweep"],
                     help="run only that leg and print its record (for profiling)")
-    ap.add_argument("--served-requests", type=int, default=128)
+    ap.add_argument("--served-requests", type=int, default=256)
     ap.add_argument("--served-seed", type=int, default=12)
-    ap.add_argument("--served-load", type=float, default=0.7)
+    ap.add_argument("--served-loads", type=float, nargs="+", default=[0.7, 0.5, 0.9],
+                    help="offered loads of the Poisson runs (first one is the headline)")
     ap.add_argument("--served-budget-gb", type=int, default=64)
     ap.add_argument("--served-lanes", type=int, default=4)
     ap.add_argument("--served-inflight", type=int, default=1024)
@@ -447,7 +562,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     if args.only:
-        leg = batched_leg if args.only == "batched" else served_leg
+        leg = {"batched": batched_leg, "served": served_leg, "sweep": sweep}[args.only]
         print(json.dumps({args.only: leg(args, ds, torch, dev)}), flush=True)
         return
     n = 1 << args.log2n
@@ -456,7 +571,10 @@ def main():
     log(f"[bench] generating 2^{args.log2n} uniform u32 keys (seed {args.seed})")
     keys = synth.uniform_u32(n, args.seed)
     src = torch.from_numpy(keys.view(np.int32)).to(dev)
-    bufs = [src.clone() for _ in range(W + K)]
+    # W warm-up, K timed, and (with stage timing) K more instrumented steps, each on its own
+    # resident copy of the unsorted input
+    nb = W + K + (0 if args.no_stage_timing else K)
+    bufs = [src.clone() for _ in range(nb)]
     del src
     plan = ds.Plan(ds.U32, False, n)
     g = plan.geometry(n)
@@ -469,15 +587,30 @@ def main():
     for i in range(W):
         plan.sort_keys(bufs[i], ws, stream)
     torch.cuda.synchronize()
-    plan.set_timing(not args.no_stage_timing)
     log(f"[bench] timing {K} steps")
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
     t0 = time.perf_counter()
-    for i in range(W, W + K):
+    evs[0].record(stream)
+    for j, i in enumerate(range(W, W + K)):
         plan.sort_keys(bufs[i], ws, stream)
+        evs[j + 1].record(stream)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    stages = plan.stage_times() if not args.no_stage_timing else {}
-    plan.set_timing(False)
+    step_ms = sorted(evs[j].elapsed_time(evs[j + 1]) for j in range(K))
+    stages = {}
+    dt_instr = None
+    if not args.no_stage_timing:
+        # per-kernel HIP events (the library brackets every launch) on K more sorts, kept out
+        # of the headline region because the events themselves cost time
+        log(f"[bench] timing {K} instrumented steps")
+        plan.set_timing(True)
+        t1 = time.perf_counter()
+        for i in range(W + K, W + 2 * K):
+            plan.sort_keys(bufs[i], ws, stream)
+        torch.cuda.synchronize()
+        dt_instr = time.perf_counter() - t1
+        stages = plan.stage_times()
+        plan.set_timing(False)
     if args.copy_calibration:
         cs = torch.empty(args.copy_calibration // 4, dtype=torch.int32, device=dev)
         cd = torch.empty_like(cs)
@@ -543,7 +676,11 @@ def main():
                                f"seed {args.seed}), keys only", "n": n,
                    "levels": g.levels, "L": g.sublist_len, "s": g.samples, "m": g.sublists,
                    "L2": g.sublist_len2, "s2": g.samples2},
+        "step_ms": {"median": round(step_ms[K // 2], 4), "min": round(step_ms[0], 4),
+                    "spread": round(step_ms[-1] - step_ms[0], 4)},
+        "instrumented_ms_per_step": round(dt_instr / K * 1e3, 4) if dt_instr else None,
         "path_hbm_gbs": round(whole_bytes / (ms_per_step * 1e-3) / 1e9, 1) if stages else None,
+        "path": path_roofline(n, kb, ms_per_step),
         "stage_ms": {k: round(v, 4) for k, v in groups.items()},
         "kernel_ms": stage_ms,
         "roofline": roofline,
