@@ -227,9 +227,9 @@ int dsort_autotune_segmented(dsort_plan_t plan, const void *d_keys, const uint32
  * no longer than dsort_segmented's segment limit for their key layout are batched with the other
  * waiting ones of the same layout (key type and values or not) into one segmented sort (their
  * items are copied to a staging block of the arena and back); longer requests run alone as
- * dsort_keys/dsort_pairs would, in place.  A launch starts only if its memory fits the arena,
- * else the oldest request waits (first come, first served), and at most `max_inflight`
- * requests run at once.  Results are exactly those of dsort_keys/dsort_pairs on each request
+ * dsort_keys/dsort_pairs would, in place.  A launch starts only if its requests' data plus its
+ * workspace fit what is left of the budget, else the oldest request waits (first come, first
+ * served), and at most `max_inflight` requests run at once.  Results are exactly those of dsort_keys/dsort_pairs on each request
  * alone.  The request's data must be complete in device memory when it is submitted (the
  * server's streams do not wait for other streams), and its buffers must stay valid and untouched
  * until dsort_poll reports it finished; two requests must not share memory. */
@@ -266,8 +266,8 @@ typedef struct {
 int dsort_server_create(dsort_server_t *out, uint64_t hbm_budget_bytes, uint32_t max_inflight,
                         uint32_t lanes);
 /* Queues a request and returns at once with its ticket.  Errors: DSORT_E_INVALID (bad type,
- * pointers or alignment), DSORT_E_CAPACITY (the request alone needs more memory than the arena
- * holds, or has no feasible plan). */
+ * pointers or alignment), DSORT_E_CAPACITY (the request's data plus its workspace exceed the
+ * budget, or it has no feasible plan). */
 int dsort_submit(dsort_server_t server, const dsort_request_t *req, uint64_t *ticket);
 /* Current state and timestamps of a ticket (never blocks).  DSORT_E_TICKET if unknown. */
 int dsort_poll(dsort_server_t server, uint64_t ticket, dsort_result_t *out);

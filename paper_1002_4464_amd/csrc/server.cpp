@@ -1,7 +1,10 @@
 // Served sort stream: the device side of the scheduler in server_core.h and its C ABI.
 //
-// A server owns one device arena (the HBM budget), `lanes` HIP streams of default priority with
-// one completion event each, and per lane a pinned host table for batch descriptors.  A plain
+// A server owns one device arena of the HBM budget, `lanes` HIP streams of default priority with
+// one completion event each, and per lane a pinned host table for batch descriptors.  A launch
+// is admitted when its requests' data plus its workspace fit what is left of the budget; the
+// workspace part is carved from the arena (the data part is reserved there too, unused, so one
+// allocator keeps the account).  A plain
 // unit runs Algorithm 1 in place on the request's buffers with a workspace block from the arena.
 // A batched unit (several small requests of one key layout) copies its members into a staging
 // block, runs one segmented sort over them (each request one segment), and copies the results
@@ -63,9 +66,17 @@ class HipExecutor : public srv::Executor {
         return seg_limit(key_type, values);
     }
 
-    // Arena bytes: plain = the sort's workspace; batched = segmented workspace, then staging
-    // keys, staging values, the request pointer tables and the offsets.
+    // Budget bytes of a unit: the requests' own data (counted, not allocated: it lives in the
+    // callers' buffers) plus the arena block it takes.  Arena block: plain = the sort's
+    // workspace; batched = segmented workspace, then staging keys, staging values, the request
+    // pointer tables and the offsets.
     uint64_t unit_bytes(const srv::Unit &u) const override {
+        const uint64_t data = u.total * (key_bytes_of(u.key_type) + (u.values ? 4u : 0u));
+        const uint64_t blk = block_bytes(u);
+        return blk ? data + blk : 0;
+    }
+
+    uint64_t block_bytes(const srv::Unit &u) const {
         if (!u.batched) {
             if (u.total <= 1) return 256;
             Geom g;
