@@ -906,7 +906,8 @@ struct GatherArgs {
     const uint4 *buckets;    // {begin, size, first piece, pieces}
     const uint32_t *pdst;    // bucket-major l_ij
     const uint32_t *psrc;    // bucket-major source position of A_ij
-    const uint32_t *count;   // per class: buckets on its list
+    uint32_t *count;         // per class: buckets on its list; the class's work-queue
+                             // counter sits 2 * kMaxClasses entries further on
     const uint32_t *list;    // per class: bucket indices
     uint32_t stride;
     uint32_t n_total;
@@ -935,7 +936,10 @@ template <class K, bool V, int CAP> struct GatherE {
 // Steps 8 and 9 fused, merge-sort flavour: the pieces of a bucket are gathered into LDS as
 // above (with their bucket positions as tie-breaks for key/value sorts), padded with key-max
 // items to a multiple of E, and sorted with the block merge sort.  One workgroup of CAP / E
-// threads per bucket of at most CAP items; persistent over the class's work list.
+// threads per bucket of at most CAP items; persistent over the class's work list, taking
+// buckets from a queue counter (zeroed by k_init) so that workgroups that are not resident at
+// first, and ones that drew small buckets, share the work evenly.  The next bucket's index is
+// requested while the current one is sorted.
 template <class K, bool V, int CAP, bool XOUT, bool XIN = false>
 __global__ __launch_bounds__((CAP / GatherE<K, V, CAP>::E), (GatherE<K, V, CAP>::wpe))
     void k_gather_bsort(GatherArgs a, uint32_t cls) {
@@ -947,16 +951,30 @@ __global__ __launch_bounds__((CAP / GatherE<K, V, CAP>::E), (GatherE<K, V, CAP>:
     __shared__ uint32_t bnd[kMaxPieces + 1], ps[kMaxPieces];
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63, w = tid >> 6, nw = BD >> 6;
+    __shared__ uint32_t slot[2];
     const uint32_t nwork = min(a.count[cls], a.stride);
     const uint32_t *list = a.list + (size_t)cls * a.stride;
+    uint32_t *queue = a.count + 2 * kMaxClasses + cls;
     const K *src = (const K *)a.src_keys;
     K *dst = (K *)a.dst_keys;
-    for (uint32_t item = blockIdx.x; item < nwork; item += gridDim.x) {
+    if (tid == 0) slot[0] = atomicAdd(queue, 1u);
+    __syncthreads();
+    for (uint32_t k = 0;; k ^= 1) {
+        // slot[k] was written before the previous barrier; slot[k ^ 1] was last read at the
+        // top of the previous iteration, before its barriers
+        const uint32_t item = slot[k];
+        if (item >= nwork) break;
+        uint32_t nxt = 0;
+        if (tid == 0) nxt = atomicAdd(queue, 1u);
         const uint4 b = a.buckets[list[item]];
         const uint32_t begin = b.x, total = b.y, pbase = b.z, np = b.w;
         if (total == 0 || total > CAP || np > kMaxPieces || np == 0 ||
             (uint64_t)begin + total > a.n_total) {
-            if (tid == 0) atomicOr(a.status, 8u);
+            if (tid == 0) {
+                atomicOr(a.status, 8u);
+                slot[k ^ 1] = nxt;
+            }
+            __syncthreads();
             continue;
         }
         __syncthreads();
@@ -1027,13 +1045,18 @@ __global__ __launch_bounds__((CAP / GatherE<K, V, CAP>::E), (GatherE<K, V, CAP>:
                 if (x < total) a.dst_vals[begin + x] = lv[pos[q]];
             }
         }
+        if (tid == 0) slot[k ^ 1] = nxt;
+        __syncthreads();
     }
 }
 
 // ------------------------------------------------------------------------------ misc
 
+// The workspace's first 256 bytes: [0] status flags, [1, 1 + kMaxClasses) the final buckets'
+// class counters, [1 + kMaxClasses, 1 + 2 kMaxClasses) those of a segmented sort's one-piece
+// buckets, and 2 kMaxClasses entries after each counter its class's work-queue counter.
 __global__ void k_init(uint32_t *status) {
-    if (threadIdx.x <= 2u * kMaxClasses && blockIdx.x == 0) status[threadIdx.x] = 0;
+    if (threadIdx.x <= 4u * kMaxClasses && blockIdx.x == 0) status[threadIdx.x] = 0;
 }
 
 // Long-segment classes of a segmented sort, as the set-up kernel sees them.
@@ -1125,9 +1148,13 @@ __global__ __launch_bounds__(1024) void k_seg_prepare(const uint64_t *off, uint3
         }
 }
 
-// Clears the work-list counters of the final buckets (between the classes of a segmented sort).
+// Clears the work-list counters of the final buckets and their queue counters (between the
+// classes of a segmented sort).
 __global__ void k_clear_counters(uint32_t *count, uint32_t n) {
-    if (threadIdx.x < n) count[threadIdx.x] = 0;
+    if (threadIdx.x < n) {
+        count[threadIdx.x] = 0;
+        count[threadIdx.x + 2 * kMaxClasses] = 0;
+    }
 }
 
 // ------------------------------------------------------------------------------ host driver
@@ -1195,6 +1222,21 @@ template <> struct ClassCaps<C128> {
 
 constexpr uint32_t kNumCUs = 256;
 
+// Workgroups of `kernel` (blocks of `block` threads, static LDS only) that the current device
+// holds at once, from the runtime's occupancy calculator; `fallback` when it cannot say.
+template <class F> uint32_t resident_blocks(F kernel, uint32_t block, uint32_t fallback) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, (int)block, 0) !=
+            hipSuccess ||
+        cus <= 0 || per_cu <= 0) {
+        (void)hipGetLastError();  // not a launch failure: keep it out of the next check
+        return fallback;
+    }
+    return (uint32_t)cus * (uint32_t)per_cu;
+}
+
 template <class K, bool V, bool F32> struct Pipeline {
     using R = Tr<K, V>;
     using SC = typename R::SC;
@@ -1218,8 +1260,9 @@ template <class K, bool V, bool F32> struct Pipeline {
         return c;
     }
 
-    // One persistent launch per size class, each sized to fill the chip at its occupancy
-    // (the smaller of what LDS and the wave slots allow per CU).
+    // One persistent launch per size class, each exactly as large as the device can hold at
+    // once (the runtime's occupancy figure, which counts registers as well as LDS and wave
+    // slots: a grid beyond it would run its surplus as a second, serial round).
     template <uint32_t I, bool XIN = false>
     static int gather_classes(const GatherArgs &a, hipStream_t st, Timing *tm) {
         if constexpr (I < CC::n) {
@@ -1230,7 +1273,9 @@ template <class K, bool V, bool F32> struct Pipeline {
             constexpr uint32_t gby_lds = 163840u / glds;
             constexpr uint32_t gby_waves = 32u / ((GBD + 63) / 64);
             constexpr uint32_t gocc = gby_lds < gby_waves ? gby_lds : gby_waves;
-            const uint32_t grid = min(a.stride, kNumCUs * (gocc ? gocc : 1u));
+            static const uint32_t slots = resident_blocks(k_gather_bsort<K, V, CAP, F32, XIN>,
+                                                          GBD, kNumCUs * (gocc ? gocc : 1u));
+            const uint32_t grid = min(a.stride, slots);
             DS_LAUNCH("s89_gather_sort", (k_gather_bsort<K, V, CAP, F32, XIN>), dim3(grid),
                       dim3(GBD), a, I);
             return gather_classes<I + 1, XIN>(a, st, tm);
