@@ -49,8 +49,7 @@ STAGE_GROUPS = {
     "step4 sample sort": ["s4_sample_sort", "s4_sample_merge"],
     "steps5-6 rank": ["s56_rank"],
     "step7 scan": ["s7_scan_colsum", "s7_scan_mid", "s7_scan_update", "s7_scan"],
-    "step8 relocate": ["s8_relocate"],
-    "level2 steps1-3": ["l2_s123_local_sort"],
+    "step8 + level2 steps1-3": ["s8_l2_s123_gather_sort"],
     "level2 step4": ["l2_s4_sample_sort", "l2_s4_sample_merge"],
     "level2 steps5-6": ["l2_s56_rank"],
     "level2 step7": ["l2_s7_scan"],
@@ -69,8 +68,7 @@ def group_bytes(group: str, n: int, g, kb: int) -> float:
         "steps1-3 local sort + sampling": 2 * n * kb + m1s1 * sb,
         "step4 sample sort": 2 * m1s1 * sb,
         "steps5-6 rank": n * kb + m1s1 * (sb + 4),
-        "step8 relocate": 2 * n * kb + 2 * m1s1 * 4,
-        "level2 steps1-3": 2 * n * kb + m2s2 * sb,
+        "step8 + level2 steps1-3": 2 * n * kb + 2 * m1s1 * 4 + m2s2 * sb,
         "level2 steps5-6": n * kb + m2s2 * (sb + 4),
         "steps8-9 gather + bucket sort": 2 * n * kb,
     }.get(group, 0.0)
@@ -447,10 +445,10 @@ def _group_of(kernel: str, seen: dict) -> str:
     if name.startswith("k_tile_radix") or name.startswith("void k_tile_radix") or \
             (name.startswith("void k_tile<") and ", 0," in name):
         seen["tile"] = seen.get("tile", 0) + 1
-        return "steps1-3 local sort + sampling" if seen["tile"] % 2 == 1 else "level2 steps1-3"
+        return "steps1-3 local sort + sampling" if seen["tile"] % 2 == 1 else \
+            "step8 + level2 steps1-3"
     for key, grp in (("k_gather", "steps8-9 gather + bucket sort"),
                      ("k_tile<", "steps8-9 gather + bucket sort"),
-                     ("k_relocate", "step8 relocate"),
                      ("k_rank", "steps5-6 rank"),
                      ("k_sort_samples", "step4 sample sort"),
                      ("k_merge_round", "step4 sample sort"),

@@ -10,8 +10,8 @@
 //                         sorted sublist, write a_ij.
 //   k_scan_*              Step 7: bucket-major exclusive prefix sum of the m x s matrix
 //                         (column sums, scan of the column sums, update of every column).
-//   k_relocate            Step 8 of a first level that feeds a second one: move each piece
-//                         A_ij to l_ij.
+//   k_tile<GIN>           Step 8 of a first level fused into Steps 1-3 of the second: each
+//                         second-level sublist is gathered from the first level's pieces.
 //   k_gather_bsort        Steps 8-9 fused: one workgroup per bucket gathers its pieces into LDS
 //                         and sorts them (one launch per bucket size class).
 //   k_tile<MODE_FINAL>    the whole input when it fits one workgroup.
@@ -168,6 +168,7 @@ struct SegView {
 
 struct TileLoc {
     uint32_t g, i, seg_begin, seg_size, tile0, m;
+    uint32_t piece0, pieces;  // the segment's piece table (bucket tables: {.., first piece, pieces})
 };
 
 __device__ __forceinline__ bool locate_tile(const SegView &sv, uint32_t L, uint32_t t,
@@ -176,6 +177,7 @@ __device__ __forceinline__ bool locate_tile(const SegView &sv, uint32_t L, uint3
         const uint32_t m = (sv.n_single + L - 1) / L;
         if (t >= m) return false;
         o.g = 0; o.i = t; o.seg_begin = 0; o.seg_size = sv.n_single; o.tile0 = 0; o.m = m;
+        o.piece0 = 0; o.pieces = 0;
         return true;
     }
     if (t >= sv.tile_off[sv.G] || sv.tile_off[sv.G] > sv.max_tiles) return false;
@@ -191,6 +193,8 @@ __device__ __forceinline__ bool locate_tile(const SegView &sv, uint32_t L, uint3
     const uint4 d = sv.seg[lo];
     o.seg_begin = d.x;
     o.seg_size = d.y;
+    o.piece0 = d.z;
+    o.pieces = d.w;
     // Defensive: tables written by earlier kernels must describe tiles inside the array.
     if ((uint64_t)d.x + d.y > sv.n_total || (uint64_t)o.i * L >= d.y) return false;
     return true;
@@ -389,16 +393,142 @@ struct TileArgs {
     uint32_t s;      // MODE_SAMPLE: samples per sublist
     void *samples;   // MODE_SAMPLE: m*s composites, row = global tile index
     uint32_t *status;
+    const uint32_t *pdst;  // GIN: bucket-major destinations l_ij of the previous level's pieces
+    const uint32_t *psrc;  // GIN: their source positions in src_keys / src_vals
+};
+
+// Sublists of a second level read straight from the pieces of the first (Step 8 of the first
+// level fused into Step 1 of the second): item x of a level-1 bucket is item x - l_ij of the
+// piece A_ij with l_ij <= x < l_(i+1)j.  The pieces that cover one tile are staged in LDS
+// kTilePieces at a time; each wave streams its share of the chunk's items, every lane
+// following the piece its item is in, and `store(x, source index)` puts item x in place.
+constexpr uint32_t kTilePieces = 1024;
+
+// Largest p < np with pdst[p] - base <= x (pdst[0] - base is 0 for a bucket's first piece).
+// Wave-cooperative search over global memory: the nl lanes of the (whole) wave probe nl
+// evenly spaced positions at once, cutting the range nl + 1 ways per round; every lane
+// returns the answer.
+__device__ __forceinline__ uint32_t wave_piece_search(const uint32_t *pdst, uint32_t np,
+                                                      uint32_t base, uint32_t x) {
+    const uint32_t nl = min(64u, blockDim.x), lane = threadIdx.x & (nl - 1);
+    uint32_t lo = 0, hi = np;  // pdst[lo] qualifies; the answer lies in [lo, hi)
+    while (hi - lo > 1) {
+        const uint32_t step = (hi - lo + nl) / (nl + 1);
+        const uint32_t p = lo + (lane + 1) * step;
+        const bool ok = p < hi && pdst[p] - base <= x;
+        const uint64_t mask = __ballot(ok);  // the qualifying probes are a prefix of the lanes
+        lo += (mask ? 64u - (uint32_t)__clzll(mask) : 0u) * step;
+        hi = min(hi, lo + step);
+    }
+    return lo;
+}
+
+template <class F>
+__device__ __forceinline__ void tile_gather(const uint32_t *pdst, const uint32_t *psrc,
+                                            uint32_t bucket_begin, uint32_t x0, uint32_t count,
+                                            uint32_t p_first, uint32_t p_last, uint32_t *tb,
+                                            uint32_t *sb, F store) {
+    // lanes per wave (blocks of fewer than 64 threads are one partial wave)
+    const uint32_t wl = min(64u, blockDim.x), tid = threadIdx.x;
+    const uint32_t lane = tid & (wl - 1), w = tid / wl, nw = blockDim.x / wl;
+    for (uint32_t c = p_first; c <= p_last; c += kTilePieces) {
+        const uint32_t nk = min(kTilePieces, p_last + 1 - c);
+        __syncthreads();  // the previous chunk (or caller) is done with tb / sb
+        for (uint32_t k = tid; k <= nk; k += blockDim.x) {
+            uint32_t b = count;  // the tile's end closes the last piece
+            if (c + k <= p_last) {
+                const uint32_t at = pdst[c + k] - bucket_begin;  // offset in the bucket
+                b = min(max(at, x0) - x0, count);
+                if (k < nk) sb[k] = psrc[c + k] - at + x0;  // + x: source of tile item x
+            }
+            tb[k] = b;
+        }
+        __syncthreads();
+        const uint32_t lo = tb[0], hi = tb[nk];
+        const uint32_t span = ((hi - lo + nw - 1) / nw + wl - 1) / wl * wl;
+        const uint32_t xs = lo + w * span, xe = min(hi, xs + span);
+        if (xs >= xe) continue;
+        uint32_t p = 0;
+        {
+            uint32_t l = 0, h = nk - 1;  // largest k with tb[k] <= item
+            const uint32_t xi = min(xs + lane, xe - 1);
+            while (l < h) {
+                const uint32_t mid = (l + h + 1) >> 1;
+                if (tb[mid] <= xi) l = mid; else h = mid - 1;
+            }
+            p = l;
+        }
+        for (uint32_t row = xs; row < xe; row += 4 * wl) {
+            uint32_t si[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t xu = row + wl * u + lane;
+                if (xu < xe) {
+                    while (xu >= tb[p + 1]) ++p;
+                    si[u] = sb[p] + xu;
+                }
+            }
+            store.template run<4>(row + lane, wl, xe, si);
+        }
+    }
+}
+
+// Stores of tile_gather: keys into the LDS sort array (as elements carrying their tile
+// position), values into a plain u32 LDS array.  Source indices past the array are never read.
+template <class K, class R, class T> struct GatherKeys {
+    const K *src;
+    T *lds;
+    uint32_t n_total;
+    // items x0 + stride * u (u < U) below xe come from source indices si[u]
+    template <int U>
+    __device__ __forceinline__ void run(uint32_t x0, uint32_t stride, uint32_t xe,
+                                        const uint32_t (&si)[U]) const {
+        K v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t xu = x0 + stride * u;
+            v[u] = (xu < xe && si[u] < n_total) ? src[si[u]] : KeyMax<K>::v;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t xu = x0 + stride * u;
+            if (xu < xe) lds[pidx<T>(xu)] = R::make(v[u], xu);
+        }
+    }
+};
+struct GatherVals {
+    const uint32_t *src;
+    uint32_t *lv;
+    uint32_t n_total;
+    template <int U>
+    __device__ __forceinline__ void run(uint32_t x0, uint32_t stride, uint32_t xe,
+                                        const uint32_t (&si)[U]) const {
+        uint32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t xu = x0 + stride * u;
+            v[u] = (xu < xe && si[u] < n_total) ? src[si[u]] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t xu = x0 + stride * u;
+            if (xu < xe) lv[xu] = v[u];
+        }
+    }
 };
 
 // MODE_SAMPLE (Steps 1-3): one workgroup per sublist of L items; writes the sorted sublist in
 // place and its s samples.  MODE_FINAL (Step 9): one workgroup per segment of at most CAP
 // items, sorted from src into dst (which may alias).  XIN/XOUT apply the f32 order map.
-template <class K, bool V, int E, int CAP, int MODE, bool XIN, bool XOUT>
+// GIN (MODE_SAMPLE, second level): the sublist is gathered from the previous level's pieces
+// (see tile_gather) and the sorted sublist goes to dst, which must not alias src.
+template <class K, bool V, int E, int CAP, int MODE, bool XIN, bool XOUT, bool GIN = false>
 __global__ __launch_bounds__(CAP / E) void k_tile(TileArgs a) {
     using R = Tr<K, V>;
     using T = typename R::T;
+    static_assert(!GIN || (MODE == MODE_SAMPLE && !XIN), "piece gathers feed Steps 1-3 only");
     __shared__ T lds[lds_elems<T>(CAP) + 1];
+    __shared__ uint32_t tb[GIN ? kTilePieces + 1 : 1], sb[GIN ? kTilePieces : 1], pr[2];
     const uint32_t tid = threadIdx.x;
     const uint32_t bd = blockDim.x;
 
@@ -422,16 +552,33 @@ __global__ __launch_bounds__(CAP / E) void k_tile(TileArgs a) {
     }
 
     const K *src = (const K *)a.src_keys;
-    for (uint32_t i = tid; i < P; i += bd) {
-        T e;
-        if (i < count) {
-            K k = src[begin + i];
-            if (XIN) k = (K)f32_in((uint32_t)k);
-            e = R::make(k, i);
-        } else {
-            e = R::pad(i);
+    uint32_t p_first = 0, p_last = 0;
+    if (GIN) {
+        // pieces holding the tile's first and last items (one wave each, or one wave both)
+        const uint32_t wl = min(64u, bd);
+        for (uint32_t q = tid / wl; q < 2; q += bd / wl) {
+            const uint32_t x = loc.i * a.L + (q == 0 ? 0u : count - 1);
+            const uint32_t p = wave_piece_search(a.pdst + loc.piece0, loc.pieces, loc.seg_begin, x);
+            if ((tid & (wl - 1)) == 0) pr[q] = p;
         }
-        lds[pidx<T>(i)] = e;
+        __syncthreads();
+        p_first = pr[0];
+        p_last = pr[1];
+        tile_gather(a.pdst + loc.piece0, a.psrc + loc.piece0, loc.seg_begin, loc.i * a.L, count,
+                    p_first, p_last, tb, sb, GatherKeys<K, R, T>{src, lds, a.sv.n_total});
+        for (uint32_t i = count + tid; i < P; i += bd) lds[pidx<T>(i)] = R::pad(i);
+    } else {
+        for (uint32_t i = tid; i < P; i += bd) {
+            T e;
+            if (i < count) {
+                K k = src[begin + i];
+                if (XIN) k = (K)f32_in((uint32_t)k);
+                e = R::make(k, i);
+            } else {
+                e = R::pad(i);
+            }
+            lds[pidx<T>(i)] = e;
+        }
     }
     __syncthreads();
     block_sort<T, E, V>(lds, P);  // key/value elements carry their load position
@@ -461,7 +608,12 @@ __global__ __launch_bounds__(CAP / E) void k_tile(TileArgs a) {
     if (V) {
         __syncthreads();
         uint32_t *lv = (uint32_t *)lds;
-        for (uint32_t i = tid; i < count; i += bd) lv[i] = a.src_vals[begin + i];
+        if (GIN)
+            tile_gather(a.pdst + loc.piece0, a.psrc + loc.piece0, loc.seg_begin, loc.i * a.L,
+                        count, p_first, p_last, tb, sb,
+                        GatherVals{a.src_vals, lv, a.sv.n_total});
+        else
+            for (uint32_t i = tid; i < count; i += bd) lv[i] = a.src_vals[begin + i];
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < E; ++q) {
@@ -833,70 +985,7 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *counts, cons
     scan_rows(counts, offs, pdst, psrc, 0u, m, i0, i1, s, 0u, L, colstart, C, Lm);
 }
 
-// ------------------------------------------------------------------------------ Step 8
-
-// One workgroup per sorted sublist: item r of piece j (ranks [st_j, st_{j+1})) moves to
-// l_ij + r - st_j.  Each wave streams a contiguous slice of the sublist 64 items at a time (loads
-// coalesced; stores contiguous within a piece), every lane following the piece its item is in.
-// Pads (r >= count) are never written.  Used between the two levels.
-template <class K, bool V>
-__global__ __launch_bounds__(256) void k_relocate(const K *src, K *dst, const uint32_t *src_vals,
-                                                  uint32_t *dst_vals, const uint32_t *counts,
-                                                  const uint32_t *offs, SegView sv, uint32_t L,
-                                                  uint32_t s) {
-    __shared__ uint32_t st[1025], of[1024];
-    TileLoc loc;
-    if (!locate_tile(sv, L, blockIdx.x, loc)) return;
-    const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
-    const uint32_t base = loc.seg_begin + loc.i * L;
-    const uint32_t count = min(L, loc.seg_size - loc.i * L);
-    const size_t row = (size_t)(loc.tile0 + loc.i) * s;
-    for (uint32_t j = tid; j < s; j += blockDim.x) {
-        st[j] = counts[row + j];
-        of[j] = offs[row + j];
-    }
-    const uint32_t tot = lds_scan(st, s);
-    if (tid == 0) st[s] = tot;
-    __syncthreads();
-    const uint32_t span = ((count + nw - 1) / nw + 63) & ~63u;
-    const uint32_t r0 = w * span, r1 = min(count, r0 + span);
-    if (r0 >= r1) return;
-    uint32_t p;
-    {
-        uint32_t lo = 0, hi = s - 1;  // largest p with st[p] <= r
-        const uint32_t r = min(r0 + lane, r1 - 1);
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (st[mid] <= r) lo = mid; else hi = mid - 1;
-        }
-        p = lo;
-    }
-    for (uint32_t rw = r0; rw < r1; rw += 4 * 64) {
-        K v[4];
-        uint32_t vv[4], d[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t r = rw + 64 * u + lane;
-            if (r < r1) {
-                while (r >= st[p + 1]) ++p;
-                d[u] = of[p] + (r - st[p]);
-                v[u] = src[base + r];
-                if (V) vv[u] = src_vals[base + r];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t r = rw + 64 * u + lane;
-            if (r < r1 && d[u] < sv.n_total) {  // defensive: offsets always lie inside the array
-                dst[d[u]] = v[u];
-                if (V) dst_vals[d[u]] = vv[u];
-            }
-        }
-    }
-}
-
 // ------------------------------------------------------------------------------ Steps 8+9
-
 
 struct GatherArgs {
     const void *src_keys;    // sorted sublists of the last level
@@ -933,8 +1022,9 @@ template <class K, bool V, int CAP> struct GatherE {
 };
 
 
-// Steps 8 and 9 fused, merge-sort flavour: the pieces of a bucket are gathered into LDS as
-// above (with their bucket positions as tie-breaks for key/value sorts), padded with key-max
+// Steps 8 and 9 fused: the pieces of a bucket are gathered into LDS, each wave streaming its
+// share of the bucket with every lane following the piece its item is in (with their bucket
+// positions as tie-breaks for key/value sorts), padded with key-max
 // items to a multiple of E, and sorted with the block merge sort.  One workgroup of CAP / E
 // threads per bucket of at most CAP items; persistent over the class's work list, taking
 // buckets from a queue counter (zeroed by k_init) so that workgroups that are not resident at
@@ -1414,7 +1504,8 @@ template <class K, bool V, bool F32> struct Pipeline {
         uint32_t *tileoff2 = g.levels == 2 ? (uint32_t *)(ws + g.o_tileoff2) : nullptr;
         const SegView sv1{nullptr, nullptr, 1, n, n, g.m1};
         // One level: the sorted sublists go to the workspace copy, and the fused Steps 8-9
-        // gather from there into keys.  Two levels: sorted in place, relocated into the copy.
+        // gather from there into keys.  Two levels: sorted in place, gathered piece by piece
+        // into the second level's sorted sublists in the copy.
         K *tiles = g.levels == 1 ? wkeys : keys;
         uint32_t *tvals = g.levels == 1 ? wvals : d_vals;
 
@@ -1451,11 +1542,9 @@ template <class K, bool V, bool F32> struct Pipeline {
             return gather_classes<0>(a, st, tm);
         }
 
-        // Step 8 into the workspace copy, then Step 9 as a second level: Algorithm 1 on every
-        // bucket of level 1, with its own fused Steps 8-9 writing the final order into keys.
-        DS_LAUNCH("s8_relocate", (k_relocate<K, V>), dim3(g.m1), dim3(256), (const K *)keys,
-                  wkeys, (const uint32_t *)d_vals, wvals, (const uint32_t *)counts,
-                  (const uint32_t *)offs, sv1, g.L1, g.s1);
+        // Step 9 as a second level: Algorithm 1 on every bucket of level 1, its sublists
+        // gathered from the level-1 pieces (Step 8 fused into Step 1) and written sorted into
+        // the workspace copy; its own fused Steps 8-9 write the final order into keys.
         const SegView sv2{buckets1, tileoff2, g.s1, 0, n, g.tiles2max};
         SC *samp2 = (SC *)(ws + g.o_samp2);
         SC *sorted2 = (SC *)(ws + g.o_samp2_sorted);
@@ -1465,8 +1554,9 @@ template <class K, bool V, bool F32> struct Pipeline {
         uint32_t *psrc2 = (uint32_t *)(ws + g.o_psrc2);
         uint4 *finals = (uint4 *)(ws + g.o_final);
         {
-            TileArgs a{wkeys, wkeys, wvals, wvals, sv2, g.L2, g.s2, samp2, status};
-            DS_LAUNCH("l2_s123_local_sort", (k_tile<K, V, TE, TCAP, MODE_SAMPLE, false, false>),
+            TileArgs a{keys, wkeys, d_vals, wvals, sv2, g.L2, g.s2, samp2, status, pdst, psrc};
+            DS_LAUNCH("s8_l2_s123_gather_sort",
+                      (k_tile<K, V, TE, TCAP, MODE_SAMPLE, false, false, true>),
                       dim3(g.tiles2max), dim3(g.L2 / TE), a);
         }
         rc = sort_samples(samp2, sorted2, nullptr, sv2, g.L2, g.s2, g.s1, 0, status, st, false, 0,
