@@ -214,7 +214,9 @@ template <class T> __device__ __forceinline__ void cmpx(T &a, T &b) {
     b = hi;
 }
 
-// Batcher's odd-even merge sort network over E registers (E a power of two).
+// Batcher's odd-even merge sort network over E registers: the network of the next power of
+// two with every comparator that touches an index >= E left out (those indices would hold
+// +infinity, which the network's low-to-high comparators never move).
 template <class T, int E> __device__ __forceinline__ void reg_sort(T (&x)[E]) {
 #pragma unroll
     for (int p = 1; p < E; p <<= 1)
@@ -249,6 +251,25 @@ template <class T> __device__ __forceinline__ T lds_at(const T *lds, uint32_t i)
         : "v"(i), "v"(i >> PadShift<T>::v), "i"(SizeLog2<T>::v));
     const DS_LDS char *base = (const DS_LDS char *)lds;
     return lds_load<T>((const DS_LDS T *)(base + off));
+}
+
+// Values of key/value sorts after the sort: once a sorted element's key has been written out,
+// the key half of its LDS slot (u32 keys: the high word of (key << 32) | position; u64 keys:
+// the unused word of the 16-byte element) holds the value whose load position is that slot's
+// index, while the position half still names the slot of the element's own value.
+template <class T> struct ValSlot;
+template <> struct ValSlot<uint64_t> {
+    static constexpr int val_word = 1, pos_word = 0, words = 2;
+};
+template <> struct ValSlot<C128> {
+    static constexpr int val_word = 3, pos_word = 2, words = 4;
+};
+template <class T> __device__ __forceinline__ void put_val(T *lds, uint32_t i, uint32_t v) {
+    ((uint32_t *)(lds + pidx<T>(i)))[ValSlot<T>::val_word] = v;
+}
+template <class T> __device__ __forceinline__ uint32_t val_of_sorted(const T *lds, uint32_t x) {
+    const uint32_t p = ((const uint32_t *)(lds + pidx<T>(x)))[ValSlot<T>::pos_word];
+    return ((const uint32_t *)(lds + pidx<T>(p)))[ValSlot<T>::val_word];
 }
 
 // Merge path: number of A items among the first `diag` outputs of the stable merge of
@@ -310,7 +331,8 @@ __device__ __forceinline__ void serial_merge(const T *lds, uint32_t ai, uint32_t
 // Sorts lds[0, P) in place (P a multiple of E, E <= P <= E * blockDim.x; lds must hold
 // lds_elems(P) + 1 elements, the last one only ever read speculatively).  Thread t owns
 // items [tE, tE+E): a register network sorts them, then merge passes double the sorted run
-// length; when P is not a power of two the last run of a pass is shorter (or has no partner).
+// length (runs of E * 2^lv items); when P / E is not a power of two the last run of a pass is
+// shorter (or has no partner).
 // All threads of the block must call it.  COMP: see MergeLess (the register network always
 // compares whole elements; only the merges may compare keys alone).
 template <class T, int E, bool COMP = false>
@@ -325,11 +347,11 @@ __device__ __forceinline__ void block_sort(T *lds, uint32_t P) {
 #pragma unroll
         for (int k = 0; k < E; ++k) lds[pidx<T>(t * E + k)] = x[k];
     }
-    for (uint32_t R = E; R < P; R <<= 1) {
+    for (uint32_t R = E, pair = 2; R < P; R <<= 1, pair <<= 1) {
         __syncthreads();
         if (act) {
             const uint32_t start = t * E;
-            const uint32_t base = start & ~(2 * R - 1);
+            const uint32_t base = (t & ~(pair - 1)) * E;  // first item of the thread's run pair
             const uint32_t diag = start - base;
             const uint32_t na = min(R, P - base);
             const uint32_t nb = min(R, P - base - na);
@@ -474,7 +496,8 @@ __device__ __forceinline__ void tile_gather(const uint32_t *pdst, const uint32_t
 }
 
 // Stores of tile_gather: keys into the LDS sort array (as elements carrying their tile
-// position), values into a plain u32 LDS array.  Source indices past the array are never read.
+// position), values into the slots' free halves (put_val).  Source indices past the array are
+// never read.
 template <class K, class R, class T> struct GatherKeys {
     const K *src;
     T *lds;
@@ -496,9 +519,9 @@ template <class K, class R, class T> struct GatherKeys {
         }
     }
 };
-struct GatherVals {
+template <class T> struct GatherVals {
     const uint32_t *src;
-    uint32_t *lv;
+    T *lds;
     uint32_t n_total;
     template <int U>
     __device__ __forceinline__ void run(uint32_t x0, uint32_t stride, uint32_t xe,
@@ -512,7 +535,7 @@ struct GatherVals {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t xu = x0 + stride * u;
-            if (xu < xe) lv[xu] = v[u];
+            if (xu < xe) put_val<T>(lds, xu, v[u]);
         }
     }
 };
@@ -593,32 +616,28 @@ __global__ __launch_bounds__(CAP / E) void k_tile(TileArgs a) {
     }
 
     K *dst = (K *)a.dst_keys;
-    uint32_t pos[E];
-#pragma unroll
+#pragma unroll 2
     for (int q = 0; q < E; ++q) {
         const uint32_t i = tid + q * bd;
         if (i < count) {
-            const T e = lds[pidx<T>(i)];
-            K k = R::key(e);
+            K k = R::key(lds[pidx<T>(i)]);
             if (XOUT) k = (K)f32_out((uint32_t)k);
             dst[begin + i] = k;
-            pos[q] = R::lpos(e);
         }
     }
-    if (V) {
+    if constexpr (V) {
         __syncthreads();
-        uint32_t *lv = (uint32_t *)lds;
         if (GIN)
             tile_gather(a.pdst + loc.piece0, a.psrc + loc.piece0, loc.seg_begin, loc.i * a.L,
                         count, p_first, p_last, tb, sb,
-                        GatherVals{a.src_vals, lv, a.sv.n_total});
+                        GatherVals<T>{a.src_vals, lds, a.sv.n_total});
         else
-            for (uint32_t i = tid; i < count; i += bd) lv[i] = a.src_vals[begin + i];
+            for (uint32_t i = tid; i < count; i += bd) put_val<T>(lds, i, a.src_vals[begin + i]);
         __syncthreads();
-#pragma unroll
+#pragma unroll 2
         for (int q = 0; q < E; ++q) {
             const uint32_t i = tid + q * bd;
-            if (i < count) a.dst_vals[begin + i] = lv[pos[q]];
+            if (i < count) a.dst_vals[begin + i] = val_of_sorted<T>(lds, i);
         }
     }
 }
@@ -1013,12 +1032,27 @@ constexpr uint32_t kMaxPieces = 256;
 #ifndef DSORT_PAIR_GATHER_WPE
 #define DSORT_PAIR_GATHER_WPE 4  // minimum waves per SIMD asked of the key/value bucket sorts
 #endif
+#ifndef DSORT_KEY_GATHER_E_6144
+#define DSORT_KEY_GATHER_E_6144 16
+#endif
+#ifndef DSORT_KEY_GATHER_E_10240
+#define DSORT_KEY_GATHER_E_10240 16
+#endif
+#ifndef DSORT_KEY_GATHER_E_12288
+#define DSORT_KEY_GATHER_E_12288 16
+#endif
 template <class K, bool V, int CAP> struct GatherE {
+    static constexpr bool keys32 = !V && sizeof(K) == 4;
     static constexpr int base =
-        sizeof(typename Tr<K, V>::T) >= 16 ? 8 : (V ? DSORT_PAIR_GATHER_E : 16);
+        sizeof(typename Tr<K, V>::T) >= 16 ? 8
+        : V                                 ? DSORT_PAIR_GATHER_E
+        : keys32 && CAP == 6144             ? DSORT_KEY_GATHER_E_6144
+        : keys32 && CAP == 10240            ? DSORT_KEY_GATHER_E_10240
+        : keys32 && CAP == 12288            ? DSORT_KEY_GATHER_E_12288
+                                            : 16;
     static constexpr int E = CAP / base > 1024 ? (CAP / 1024 <= 16 ? 16 : 32) : base;
     static constexpr int wpe = V ? DSORT_PAIR_GATHER_WPE : 1;
-    static_assert((E & (E - 1)) == 0 && CAP % E == 0 && CAP / E <= 1024, "bucket class shape");
+    static_assert(CAP % E == 0 && CAP / E <= 1024 && (CAP / E) % 64 == 0, "bucket class shape");
 };
 
 
@@ -1028,8 +1062,7 @@ template <class K, bool V, int CAP> struct GatherE {
 // items to a multiple of E, and sorted with the block merge sort.  One workgroup of CAP / E
 // threads per bucket of at most CAP items; persistent over the class's work list, taking
 // buckets from a queue counter (zeroed by k_init) so that workgroups that are not resident at
-// first, and ones that drew small buckets, share the work evenly.  The next bucket's index is
-// requested while the current one is sorted.
+// first, and ones that drew small buckets, share the work evenly.
 template <class K, bool V, int CAP, bool XOUT, bool XIN = false>
 __global__ __launch_bounds__((CAP / GatherE<K, V, CAP>::E), (GatherE<K, V, CAP>::wpe))
     void k_gather_bsort(GatherArgs a, uint32_t cls) {
@@ -1047,22 +1080,22 @@ __global__ __launch_bounds__((CAP / GatherE<K, V, CAP>::E), (GatherE<K, V, CAP>:
     uint32_t *queue = a.count + 2 * kMaxClasses + cls;
     const K *src = (const K *)a.src_keys;
     K *dst = (K *)a.dst_keys;
+    if (blockIdx.x >= nwork) return;  // more workgroups than buckets: nothing to take
     if (tid == 0) slot[0] = atomicAdd(queue, 1u);
     __syncthreads();
     for (uint32_t k = 0;; k ^= 1) {
         // slot[k] was written before the previous barrier; slot[k ^ 1] was last read at the
         // top of the previous iteration, before its barriers
-        const uint32_t item = slot[k];
+        // uniform: keeps the bucket's description in scalar registers
+        const uint32_t item = __builtin_amdgcn_readfirstlane(slot[k]);
         if (item >= nwork) break;
-        uint32_t nxt = 0;
-        if (tid == 0) nxt = atomicAdd(queue, 1u);
         const uint4 b = a.buckets[list[item]];
         const uint32_t begin = b.x, total = b.y, pbase = b.z, np = b.w;
         if (total == 0 || total > CAP || np > kMaxPieces || np == 0 ||
             (uint64_t)begin + total > a.n_total) {
             if (tid == 0) {
                 atomicOr(a.status, 8u);
-                slot[k ^ 1] = nxt;
+                slot[k ^ 1] = atomicAdd(queue, 1u);
             }
             __syncthreads();
             continue;
@@ -1108,31 +1141,32 @@ __global__ __launch_bounds__((CAP / GatherE<K, V, CAP>::E), (GatherE<K, V, CAP>:
         }
         __syncthreads();
         block_sort<T, E, V>(lds, P);  // key/value elements carry their gathered position
+        uint32_t nxt = 0;  // the next bucket, requested while this one is written out
+        if (tid == 0) nxt = atomicAdd(queue, 1u);
 
-        uint32_t pos[E];
-#pragma unroll
+        // two at a time: unrolled whole, the loads and store addresses in flight would set
+        // the kernel's register count (and so its occupancy)
+#pragma unroll 2
         for (int q = 0; q < E; ++q) {
             const uint32_t x = tid + q * BD;
             if (x < total) {
-                const T el = lds[pidx<T>(x)];
-                K kk = R::key(el);
+                K kk = R::key(lds[pidx<T>(x)]);
                 if (XOUT) kk = (K)f32_out((uint32_t)kk);
                 dst[begin + x] = kk;
-                pos[q] = R::lpos(el);
             }
         }
-        if (V) {
+        if constexpr (V) {
             __syncthreads();
-            uint32_t *lv = (uint32_t *)lds;
             for (uint32_t i = w; i < np; i += nw) {
                 const uint32_t d0 = bnd[i], len = bnd[i + 1] - d0, s0 = ps[i];
-                for (uint32_t q = lane; q < len; q += 64) lv[d0 + q] = a.src_vals[s0 + q];
+                for (uint32_t q = lane; q < len; q += 64)
+                    put_val<T>(lds, d0 + q, a.src_vals[s0 + q]);
             }
             __syncthreads();
-#pragma unroll
+#pragma unroll 2
             for (int q = 0; q < E; ++q) {
                 const uint32_t x = tid + q * BD;
-                if (x < total) a.dst_vals[begin + x] = lv[pos[q]];
+                if (x < total) a.dst_vals[begin + x] = val_of_sorted<T>(lds, x);
             }
         }
         if (tid == 0) slot[k ^ 1] = nxt;
