@@ -135,8 +135,11 @@ SegTuning seg_default_split(int key_type, bool values, uint64_t max_seg);
 // Candidate sublist lengths of the autotuner, largest first (count returned).
 int seg_candidate_L(const Caps &c, uint32_t *out);
 constexpr uint32_t kRunSmall = 1u << 31;  // run_segmented mask bit of the one-piece segments
+// fork: run the bucket size classes on side streams as well (joined before return); off for
+// callers that already run several sorts side by side.
 int run_segmented(const SegGeom &g, void *d_keys, uint32_t *d_vals, const uint64_t *d_off,
-                  void *d_ws, void *stream, Timing *tm, uint32_t mask = 0xFFFFFFFFu);
+                  void *d_ws, void *stream, Timing *tm, uint32_t mask = 0xFFFFFFFFu,
+                  bool fork = false);
 // Copies between requests' own buffers and a staging array (served-stream batches).
 int launch_pack(int key_bytes, const uint64_t *d_src_keys, const uint64_t *d_src_vals,
                 const uint64_t *d_off, uint32_t S, uint64_t total, void *stage_keys,

@@ -26,6 +26,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+
 #include "dsort_internal.h"
 
 namespace dsort {
@@ -1036,7 +1039,7 @@ constexpr uint32_t kMaxPieces = 256;
 #define DSORT_KEY_GATHER_E_6144 16
 #endif
 #ifndef DSORT_KEY_GATHER_E_10240
-#define DSORT_KEY_GATHER_E_10240 16
+#define DSORT_KEY_GATHER_E_10240 20
 #endif
 #ifndef DSORT_KEY_GATHER_E_12288
 #define DSORT_KEY_GATHER_E_12288 16
@@ -1346,6 +1349,45 @@ template <> struct ClassCaps<C128> {
 
 constexpr uint32_t kNumCUs = 256;
 
+// Side streams on which the bucket size classes of one call run side by side, so that the
+// single-bucket latency of a sparsely used class and the tail of a busy one overlap other
+// classes' work; the call's stream waits for all of them before its next launch.  One set per
+// device for the process (default priority, non-blocking), created on the first call that is
+// not being captured; a call's fork and join are enqueued under one lock, so that calls from
+// several host threads never interleave their event records.
+#ifndef DSORT_FORK_CLASSES
+#define DSORT_FORK_CLASSES 1  // 0: every class on the call's stream
+#endif
+constexpr int kForkStreams = 3;
+struct ForkSet {
+    hipStream_t side[kForkStreams];
+    hipEvent_t fork;
+    hipEvent_t join[kForkStreams];
+};
+std::mutex g_fork_mu;
+
+// The device's set (nullptr if it cannot be made now); the caller holds g_fork_mu.
+ForkSet *fork_set(hipStream_t st) {
+    static std::map<int, ForkSet> sets;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    auto it = sets.find(dev);
+    if (it != sets.end()) return &it->second;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return nullptr;
+    ForkSet f{};
+    bool ok = hipEventCreateWithFlags(&f.fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < kForkStreams && ok; ++i)
+        ok = hipStreamCreateWithFlags(&f.side[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&f.join[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        return nullptr;  // partly made objects are left alone; the call runs on one stream
+    }
+    return &sets.emplace(dev, f).first->second;
+}
+
 // Workgroups of `kernel` (blocks of `block` threads, static LDS only) that the current device
 // holds at once, from the runtime's occupancy calculator; `fallback` when it cannot say.
 template <class F> uint32_t resident_blocks(F kernel, uint32_t block, uint32_t fallback) {
@@ -1386,10 +1428,12 @@ template <class K, bool V, bool F32> struct Pipeline {
 
     // One persistent launch per size class, each exactly as large as the device can hold at
     // once (the runtime's occupancy figure, which counts registers as well as LDS and wave
-    // slots: a grid beyond it would run its surplus as a second, serial round).
+    // slots: a grid beyond it would run its surplus as a second, serial round).  Class I goes
+    // to stream cs[I].
     template <uint32_t I, bool XIN = false>
-    static int gather_classes(const GatherArgs &a, hipStream_t st, Timing *tm) {
+    static int gather_classes(const GatherArgs &a, const hipStream_t *cs, Timing *tm) {
         if constexpr (I < CC::n) {
+            hipStream_t st = cs[I];
             constexpr int CAP = (int)CC::cap[I];
             constexpr int GE = GatherE<K, V, CAP>::E;
             constexpr uint32_t GBD = CAP / GE;
@@ -1402,10 +1446,67 @@ template <class K, bool V, bool F32> struct Pipeline {
             const uint32_t grid = min(a.stride, slots);
             DS_LAUNCH("s89_gather_sort", (k_gather_bsort<K, V, CAP, F32, XIN>), dim3(grid),
                       dim3(GBD), a, I);
-            return gather_classes<I + 1, XIN>(a, st, tm);
+            return gather_classes<I + 1, XIN>(a, cs, tm);
         }
         return DSORT_OK;
     }
+
+    // The fused Steps 8-9 of one level: every size class one after another on st, or, when
+    // `fork` (and no per-kernel timing is asked for), class i on stream i mod 4 of st and the
+    // three side streams.  Segmented sorts fork: their buckets spread over all classes, and
+    // side by side the sparsely used classes fill the busy ones' tails.  Plain sorts do not:
+    // their buckets crowd into two neighbouring classes, whose persistent grids side by side
+    // only contend for the same CUs (measured slower).
+    // With join == false the side streams are left running and *forked tells whether there
+    // are any: the caller must join_side(st) before work on st that depends on them (and
+    // before returning, failed launches included).
+    template <bool XIN = false>
+    static int launch_classes(const GatherArgs &a, hipStream_t st, Timing *tm, bool fork,
+                              bool join = true, bool *forked = nullptr) {
+        hipStream_t cs[kMaxClasses];
+        for (auto &c : cs) c = st;
+        if (forked) *forked = false;
+        if (!DSORT_FORK_CLASSES || !fork || tm) return gather_classes<0, XIN>(a, cs, tm);
+        int rc;
+        {
+            std::lock_guard<std::mutex> lock(g_fork_mu);
+            ForkSet *fs = fork_set(st);
+            if (!fs) return gather_classes<0, XIN>(a, cs, tm);
+            for (uint32_t i = 0; i < (uint32_t)kMaxClasses; ++i)
+                if (i % (1 + kForkStreams)) cs[i] = fs->side[i % (1 + kForkStreams) - 1];
+            if (hipEventRecord(fs->fork, st) != hipSuccess)
+                return record_error("s89_fork", hipGetLastError());
+            for (int i = 0; i < kForkStreams; ++i)
+                if (hipStreamWaitEvent(fs->side[i], fs->fork, 0) != hipSuccess)
+                    return record_error("s89_fork", hipGetLastError());
+            if (forked) *forked = true;
+            rc = gather_classes<0, XIN>(a, cs, nullptr);
+        }
+        if (!join) return rc;
+        // joined even after a failed launch: later work on st must not overtake a side stream
+        const int rj = join_side(st);
+        return rc ? rc : rj;
+    }
+
+    // Makes st wait for everything enqueued so far on the device's side streams.
+    static int join_side(hipStream_t st) {
+        std::lock_guard<std::mutex> lock(g_fork_mu);
+        ForkSet *fs = fork_set(st);
+        if (!fs) return DSORT_OK;
+        int rj = DSORT_OK;
+        for (int i = 0; i < kForkStreams; ++i)
+            if (hipEventRecord(fs->join[i], fs->side[i]) != hipSuccess ||
+                hipStreamWaitEvent(st, fs->join[i], 0) != hipSuccess)
+                rj = record_error("s89_join", hipGetLastError());
+        return rj;
+    }
+    struct SideJoin {  // joins on scope exit when armed
+        hipStream_t st;
+        bool armed = false;
+        ~SideJoin() {
+            if (armed) (void)join_side(st);
+        }
+    };
 
     // Step 4 for one level.  G > 0 segments sorted one workgroup each, or (global) the single
     // segment's m*s samples by chunk sorts plus merge rounds ending in `sorted`.
@@ -1439,7 +1540,7 @@ template <class K, bool V, bool F32> struct Pipeline {
     // workspace copy and gathered back per bucket.
     static int run_segmented(const SegGeom &g, void *d_keys, uint32_t *d_vals,
                              const uint64_t *d_off, void *d_ws, hipStream_t st, Timing *tm,
-                             uint32_t mask) {
+                             uint32_t mask, bool fork) {
         char *ws = (char *)d_ws;
         uint32_t *status = (uint32_t *)(ws + g.o_status);
         DS_LAUNCH("init", k_init, dim3(1), dim3(64), status);
@@ -1463,11 +1564,15 @@ template <class K, bool V, bool F32> struct Pipeline {
         }
         DS_LAUNCH("seg_prepare", k_seg_prepare, dim3(1), dim3(1024), d_off, S, n,
                   (uint32_t)g.max_seg, g.small_cap, ca, small_b, spiece, scls, status);
-        if (mask & kRunSmall) {  // one-piece buckets in place: a workgroup reads its whole
-                                 // segment before writing
+        // One-piece buckets in place (a workgroup reads its whole segment before writing).
+        // When forked they keep running beside the long segments' Steps 1-7, which touch other
+        // items and other counters; the first long class's own fork and join, or `side` on the
+        // way out, joins them.
+        SideJoin side{st};
+        if (mask & kRunSmall) {
             GatherArgs a{keys, keys, d_vals, d_vals, small_b, spiece, spiece, scls.count, slists,
                          S, n, status};
-            int rc0 = gather_classes<0, F32>(a, st, tm);
+            int rc0 = launch_classes<F32>(a, st, tm, fork, false, &side.armed);
             if (rc0) return rc0;
         }
         K *wkeys = (K *)(ws + g.o_wkeys);
@@ -1504,7 +1609,7 @@ template <class K, bool V, bool F32> struct Pipeline {
                       offs, pdst, psrc, sv, q.L, q.s, finals, fcls);
             GatherArgs a{wkeys, keys, wvals, d_vals, finals, pdst, psrc, fcls.count, lists,
                          q.gmax * q.s, n, status};
-            rc = gather_classes<0>(a, st, tm);
+            rc = launch_classes(a, st, tm, fork);
             if (rc) return rc;
         }
         return DSORT_OK;
@@ -1573,7 +1678,7 @@ template <class K, bool V, bool F32> struct Pipeline {
             // Steps 8-9 fused: gather every bucket's pieces, merge them, write into keys.
             GatherArgs a{wkeys, keys, wvals, d_vals, buckets1, pdst, psrc, status + 1, lists,
                          g.final_buckets, n, status};
-            return gather_classes<0>(a, st, tm);
+            return launch_classes(a, st, tm, false);
         }
 
         // Step 9 as a second level: Algorithm 1 on every bucket of level 1, its sublists
@@ -1602,7 +1707,7 @@ template <class K, bool V, bool F32> struct Pipeline {
                   offs2, pdst2, psrc2, sv2, g.L2, g.s2, finals, cls);
         GatherArgs a{wkeys, keys, wvals, d_vals, finals, pdst2, psrc2, status + 1, lists,
                      g.final_buckets, n, status};
-        return gather_classes<0>(a, st, tm);
+        return launch_classes(a, st, tm, false);
     }
 };
 
@@ -1709,7 +1814,7 @@ int launch_pack(int key_bytes, const uint64_t *d_src_keys, const uint64_t *d_src
 }
 
 int run_segmented(const SegGeom &g, void *d_keys, uint32_t *d_vals, const uint64_t *d_off,
-                  void *d_ws, void *stream, Timing *tm, uint32_t mask) {
+                  void *d_ws, void *stream, Timing *tm, uint32_t mask, bool fork) {
     hipStream_t st = (hipStream_t)stream;
     if (g.S == 0 || g.n == 0) return DSORT_OK;
     (void)hipGetLastError();
@@ -1717,19 +1822,19 @@ int run_segmented(const SegGeom &g, void *d_keys, uint32_t *d_vals, const uint64
     switch (g.key_type) {
         case DSORT_U32:
             return g.values ? Pipeline<uint32_t, true, false>::run_segmented(g, d_keys, d_vals,
-                                                                            d_off, d_ws, st, tm, mask)
+                                                                            d_off, d_ws, st, tm, mask, fork)
                             : Pipeline<uint32_t, false, false>::run_segmented(g, d_keys, d_vals,
-                                                                             d_off, d_ws, st, tm, mask);
+                                                                             d_off, d_ws, st, tm, mask, fork);
         case DSORT_F32:
             return g.values ? Pipeline<uint32_t, true, true>::run_segmented(g, d_keys, d_vals,
-                                                                           d_off, d_ws, st, tm, mask)
+                                                                           d_off, d_ws, st, tm, mask, fork)
                             : Pipeline<uint32_t, false, true>::run_segmented(g, d_keys, d_vals,
-                                                                            d_off, d_ws, st, tm, mask);
+                                                                            d_off, d_ws, st, tm, mask, fork);
         case DSORT_U64:
             return g.values ? Pipeline<uint64_t, true, false>::run_segmented(g, d_keys, d_vals,
-                                                                            d_off, d_ws, st, tm, mask)
+                                                                            d_off, d_ws, st, tm, mask, fork)
                             : Pipeline<uint64_t, false, false>::run_segmented(g, d_keys, d_vals,
-                                                                             d_off, d_ws, st, tm, mask);
+                                                                             d_off, d_ws, st, tm, mask, fork);
         default:
             return DSORT_E_INVALID;
     }

@@ -655,7 +655,7 @@ int dsort_segmented(dsort_plan_t plan, void *d_keys, uint32_t *d_values, uint64_
     if (rc != DSORT_OK) return rc;
     if (g.total > plan->workspace) return DSORT_E_CAPACITY;
     return dsort::run_segmented(g, d_keys, d_values, d_offsets, d_workspace, stream,
-                                &plan->timing);
+                                &plan->timing, 0xFFFFFFFFu, true);
 }
 
 int dsort_keys(dsort_plan_t plan, void *d_keys, uint64_t n, void *d_workspace, void *stream) {

@@ -82,7 +82,7 @@ extern "C" int dsort_autotune_segmented(dsort_plan_t plan, const void *d_keys,
                 return DSORT_E_HIP;
             }
             r = run_segmented(g, d_scratch_keys, d_scratch_values, d_offsets, d_workspace, st,
-                              nullptr, mask);
+                              nullptr, mask, true);
             if (r != DSORT_OK) return r;
             float t_ms = 0.f;
             if (hipEventRecord(ev.b, st) != hipSuccess || hipEventSynchronize(ev.b) != hipSuccess ||
