@@ -686,7 +686,8 @@ __global__ __launch_bounds__(CAP / E) void k_sort_samples(const SC *src, SC *dst
 }
 
 // One round of a global merge sort over sorted runs of length R (R a multiple of CAP):
-// workgroup b writes outputs [b*CAP, (b+1)*CAP) of the merge of its run pair.
+// workgroup b writes outputs [b*CAP, (b+1)*CAP) of the merge of its run pair (merged in
+// registers, staged back in LDS, stored with consecutive lanes on consecutive items).
 template <class SC, int E, int CAP>
 __global__ __launch_bounds__(CAP / E) void k_merge_round(const SC *src, SC *dst, uint32_t total,
                                                          uint32_t R) {
@@ -728,31 +729,41 @@ __global__ __launch_bounds__(CAP / E) void k_merge_round(const SC *src, SC *dst,
     __syncthreads();
     const uint32_t diag = tid * E;
     const uint32_t tot = la + lb;
+    SC out[E];
     if (diag < tot) {
         const uint32_t x = merge_path<SC, true>(lds, 0, la, la, lb, diag);
-        SC out[E];
         serial_merge<SC, E, true>(lds, x, la, la + diag - x, tot, tot - 1, out);
+    }
+    __syncthreads();  // back through LDS, so that the stores below are coalesced
+    if (diag < tot) {
 #pragma unroll
         for (int k = 0; k < E; ++k)
-            if (diag + k < tot) dst[c0 + diag + k] = out[k];
+            if (diag + k < tot) lds[pidx<SC>(diag + k)] = out[k];
     }
+    __syncthreads();
+    for (uint32_t i = tid; i < tot; i += blockDim.x) dst[c0 + i] = lds[pidx<SC>(i)];
 }
 
 // ------------------------------------------------------------------------------ Steps 5-6
 
-// One workgroup per sublist; lane j locates global sample g_j = S[(j+1) m - 1] of the
+// One workgroup per sublist; it locates every global sample g_j = S[(j+1) m - 1] of the
 // sublist's segment: r_ij = #{x : (A_i[x], i*L + x) <= g_j}, a monotone predicate on the
 // sorted sublist.  The sublist's own Step-3 samples (the items at ranks (k+1) w - 1, w = L/s)
-// narrow it first: if c of them are <= g_j, then c w <= r_ij <= (c+1) w - 1, so a bisection
-// over the s samples in LDS leaves one of log2(w) probes in global memory.  Pads (x >= count)
-// are key-max items.
+// narrow it first: if c of them are <= g_j, then c w <= r_ij <= (c+1) w - 1 (a bisection over
+// the s samples in LDS, one thread per j).  Then, for w <= 128, each wave counts inside the
+// chunks of kRankBatch global samples at a time: all 64 lanes read one chunk's items with
+// coalesced loads and a ballot counts those <= g_j, the loads of the whole batch in flight
+// together (chunks shared by neighbouring samples come from cache).  Larger chunks are
+// bisected in global memory, one probe per step.  Pads (x >= count) are key-max items.
+constexpr uint32_t kRankBatch = 8;
+
 template <class K, bool V>
 __global__ __launch_bounds__(256) void k_rank(const K *keys, const void *sorted_samples,
                                               const void *tile_samples, uint32_t *counts,
                                               SegView sv, uint32_t L, uint32_t s) {
     using R = Tr<K, V>;
     using SC = typename R::SC;
-    __shared__ uint32_t rk[1025];
+    __shared__ uint32_t rk[1025], chunk[1024];
     __shared__ SC ts[1024];
     TileLoc loc;
     if (!locate_tile(sv, L, blockIdx.x, loc)) return;
@@ -771,19 +782,58 @@ __global__ __launch_bounds__(256) void k_rank(const K *keys, const void *sorted_
             const uint32_t mid = (lo + hi) >> 1;
             if (!lt(g, ts[mid])) lo = mid + 1; else hi = mid;
         }
-        uint32_t r = L;
-        if (lo < s) {
-            uint32_t a = lo * w, b = (lo + 1) * w - 1;
+        chunk[j] = lo;
+        if (lo == s) rk[j + 1] = L;  // above every sample: above every item
+    }
+    if (threadIdx.x == 0) rk[0] = 0;
+    __syncthreads();
+    if (w <= 128) {
+        const uint32_t lane = threadIdx.x & 63, nwv = blockDim.x >> 6;
+        const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        for (uint32_t j0 = wv * kRankBatch; j0 < s; j0 += nwv * kRankBatch) {
+            K v[kRankBatch][2];
+            uint32_t cc[kRankBatch];  // wave-uniform chunk of each global sample of the batch
+#pragma unroll
+            for (uint32_t u = 0; u < kRankBatch; ++u)
+                cc[u] = j0 + u < s ? __builtin_amdgcn_readfirstlane(chunk[j0 + u]) : s;
+#pragma unroll
+            for (uint32_t u = 0; u < kRankBatch; ++u) {
+                const uint32_t c = cc[u];
+#pragma unroll
+                for (uint32_t q = 0; q < 2; ++q) {
+                    const uint32_t y = q * 64 + lane, x = c * w + y;  // item of the sublist
+                    v[u][q] = (c < s && y < w && x < count) ? keys[base + x] : KeyMax<K>::v;
+                }
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kRankBatch; ++u) {
+                const uint32_t j = j0 + u, c = cc[u];
+                if (c >= s) continue;
+                const SC g = S[(size_t)(j + 1) * loc.m - 1];
+                uint32_t le = 0;
+#pragma unroll
+                for (uint32_t q = 0; q < 2; ++q) {
+                    const uint32_t y = q * 64 + lane;
+                    const bool in = y < w && !lt(g, R::samp(v[u][q], p0 + c * w + y));
+                    le += (uint32_t)__popcll(__ballot(in));
+                }
+                if (lane == 0) rk[j + 1] = c * w + le;
+            }
+        }
+    } else {
+        for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) {
+            const uint32_t c = chunk[j];
+            if (c == s) continue;
+            const SC g = S[(size_t)(j + 1) * loc.m - 1];
+            uint32_t a = c * w, b = (c + 1) * w - 1;
             while (a < b) {
                 const uint32_t x = (a + b) >> 1;
                 const K kx = x < count ? keys[base + x] : KeyMax<K>::v;
                 if (!lt(g, R::samp(kx, p0 + x))) a = x + 1; else b = x;
             }
-            r = a;
+            rk[j + 1] = a;
         }
-        rk[j + 1] = r;
     }
-    if (threadIdx.x == 0) rk[0] = 0;
     __syncthreads();
     uint32_t *row = counts + (size_t)(loc.tile0 + loc.i) * s;
     for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) row[j] = rk[j + 1] - rk[j];
@@ -974,35 +1024,45 @@ __global__ __launch_bounds__(256) void k_scan_partial(const uint32_t *counts, ui
     }
 }
 
-__global__ __launch_bounds__(256) void k_scan_mid(uint32_t *partial, uint32_t nrb, uint32_t m,
-                                                  uint32_t s, uint32_t n, uint4 *buckets,
-                                                  uint32_t *tile_off_next, uint32_t L_next,
-                                                  Classes cls) {
+// (b): groups of s threads each take a contiguous share of the row blocks of every column:
+// column sums per share, their prefix across shares, then each share's row-block prefixes
+// written back into `partial` (column-relative; k_scan_apply adds the bucket's start).
+__global__ __launch_bounds__(1024) void k_scan_mid(uint32_t *partial, uint32_t nrb, uint32_t m,
+                                                   uint32_t s, uint32_t n, uint4 *buckets,
+                                                   uint32_t *tile_off_next, uint32_t L_next,
+                                                   Classes cls) {
     __shared__ uint32_t colsum[1024], colbase[1024], tmp[1024];
-    for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) {
-        uint32_t run = 0;
-        for (uint32_t b = 0; b < nrb; ++b) {
-            const uint32_t x = partial[(size_t)b * s + j];
-            partial[(size_t)b * s + j] = run;
-            run += x;
-        }
-        colsum[j] = run;
-        colbase[j] = run;
+    const uint32_t ng = blockDim.x / s;  // s divides blockDim (both powers of two, s <= 1024)
+    const uint32_t grp = threadIdx.x / s, j = threadIdx.x % s;
+    const uint32_t per = (nrb + ng - 1) / ng;
+    const uint32_t b0 = min(nrb, grp * per), b1 = min(nrb, b0 + per);
+    uint32_t own = 0;
+    for (uint32_t b = b0; b < b1; ++b) own += partial[(size_t)b * s + j];
+    tmp[grp * s + j] = own;
+    __syncthreads();
+    uint32_t run = 0;
+    for (uint32_t q = 0; q < grp; ++q) run += tmp[q * s + j];
+    if (grp == ng - 1) {
+        colsum[j] = run + own;
+        colbase[j] = run + own;
     }
-    lds_scan(colbase, s);
-    for (uint32_t j = threadIdx.x; j < s; j += blockDim.x)
-        for (uint32_t b = 0; b < nrb; ++b) partial[(size_t)b * s + j] += colbase[j];
+    for (uint32_t b = b0; b < b1; ++b) {
+        const uint32_t x = partial[(size_t)b * s + j];
+        partial[(size_t)b * s + j] = run;
+        run += x;
+    }
+    lds_scan(colbase, s);  // (starts with a barrier: tmp is free again after it)
     emit_buckets(colsum, colbase, s, 0u, n, 0u, m, buckets, tile_off_next, L_next, tmp, cls, 0u);
 }
 
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *counts, const uint32_t *partial,
-                                                    uint32_t *offs, uint32_t *pdst, uint32_t *psrc,
-                                                    uint32_t m, uint32_t s, uint32_t RB,
-                                                    uint32_t L) {
+                                                    const uint4 *buckets, uint32_t *offs,
+                                                    uint32_t *pdst, uint32_t *psrc, uint32_t m,
+                                                    uint32_t s, uint32_t RB, uint32_t L) {
     __shared__ uint32_t colstart[1024], C[kScanLds], Lm[kScanLds];
     const uint32_t i0 = blockIdx.x * RB, i1 = min(m, i0 + RB);
     for (uint32_t j = threadIdx.x; j < s; j += blockDim.x)
-        colstart[j] = partial[(size_t)blockIdx.x * s + j];
+        colstart[j] = buckets[j].x + partial[(size_t)blockIdx.x * s + j];
     __syncthreads();
     scan_rows(counts, offs, pdst, psrc, 0u, m, i0, i1, s, 0u, L, colstart, C, Lm);
 }
@@ -1412,6 +1472,8 @@ template <class K, bool V, bool F32> struct Pipeline {
     static constexpr int FCAP = FE * 1024;                            // bucket capacity
     static constexpr int SE = sizeof(SC) >= 16 ? 8 : 16;
     static constexpr int SCAP = SE * 1024;
+    static constexpr int ME = SE / 2;  // merge rounds: half the tile, two workgroups per CU
+    static constexpr int MCAP = ME * 1024;
     using T = typename R::T;
     using CC = ClassCaps<T>;
     static_assert(CC::cap[CC::n - 1] == (uint32_t)FCAP, "last class must be the bucket capacity");
@@ -1525,7 +1587,8 @@ template <class K, bool V, bool F32> struct Pipeline {
         DS_LAUNCH(name, (k_sort_samples<SC, SE, SCAP>), dim3(chunks), dim3(SCAP / SE), samp, x,
                   sv, L, s, total, status);
         for (uint32_t run = SCAP; run < total; run <<= 1) {
-            DS_LAUNCH(name_merge, (k_merge_round<SC, SE, SCAP>), dim3(chunks), dim3(SCAP / SE),
+            DS_LAUNCH(name_merge, (k_merge_round<SC, ME, MCAP>), dim3((total + MCAP - 1) / MCAP),
+                      dim3(MCAP / ME),
                       (const SC *)x, y, total, run);
             SC *t = x;
             x = y;
@@ -1668,11 +1731,11 @@ template <class K, bool V, bool F32> struct Pipeline {
         uint32_t *lists = (uint32_t *)(ws + g.o_lists);
         const Classes cls = classes(status, lists, g.final_buckets);
         Classes none{};
-        DS_LAUNCH("s7_scan_mid", k_scan_mid, dim3(1), dim3(256), partial, g.scan_nrb, g.m1, g.s1,
-                  n, buckets1, tileoff2, g.L2, g.levels == 1 ? cls : none);
+        DS_LAUNCH("s7_scan_mid", k_scan_mid, dim3(1), dim3(1024), partial, g.scan_nrb, g.m1,
+                  g.s1, n, buckets1, tileoff2, g.L2, g.levels == 1 ? cls : none);
         DS_LAUNCH("s7_scan_update", k_scan_apply, dim3(g.scan_nrb), dim3(256),
-                  (const uint32_t *)counts, (const uint32_t *)partial, offs, pdst, psrc, g.m1,
-                  g.s1, g.scan_rb, g.L1);
+                  (const uint32_t *)counts, (const uint32_t *)partial, (const uint4 *)buckets1,
+                  offs, pdst, psrc, g.m1, g.s1, g.scan_rb, g.L1);
 
         if (g.levels == 1) {
             // Steps 8-9 fused: gather every bucket's pieces, merge them, write into keys.
