@@ -145,8 +145,14 @@ int dsort_plan_geometry(dsort_plan_t plan, uint64_t n, dsort_geometry_t *out);
  * The plan must have been made with max_segments >= num_segments and max_items >= n; the
  * workspace is the plan's.  Bad offsets are caught on the device and reported in the uint32
  * status word at workspace offset `off_status` (0 = clean run): offsets that decrease or
- * exceed n set bit 16 and then no segment is sorted; a segment longer than max_segment sets
- * bit 32 and is left as it is (the others are sorted).
+ * exceed n set the flag 0x10 and then no segment is sorted; a segment longer than max_segment
+ * sets the flag 0x20 and is left as it is (the others are sorted).
+ *
+ * Streams: the call is ordered on `stream` like any other work on it.  Internally its bucket
+ * sorts may also run on side streams (three per device, created by the library on the first
+ * call made outside stream capture and kept for the process); the call ends by enqueueing on
+ * `stream` a wait for them, so work enqueued on `stream` afterwards sees the sorted result.
+ * Calls from several host threads are safe; their bucket sorts then share the side streams.
  * Errors: DSORT_E_INVALID (bad plan or pointer, misalignment, values given to a keys-only plan
  * or missing for a pairs plan, n or num_segments above the plan's), DSORT_E_UNSUPPORTED
  * (max_segment above segment_limit), DSORT_E_HIP.  n = 0 or num_segments = 0 is a no-op. */

@@ -755,7 +755,10 @@ __global__ __launch_bounds__(CAP / E) void k_merge_round(const SC *src, SC *dst,
 // coalesced loads and a ballot counts those <= g_j, the loads of the whole batch in flight
 // together (chunks shared by neighbouring samples come from cache).  Larger chunks are
 // bisected in global memory, one probe per step.  Pads (x >= count) are key-max items.
-constexpr uint32_t kRankBatch = 8;
+#ifndef DSORT_RANK_BATCH
+#define DSORT_RANK_BATCH 8
+#endif
+constexpr uint32_t kRankBatch = DSORT_RANK_BATCH;
 
 template <class K, bool V>
 __global__ __launch_bounds__(256) void k_rank(const K *keys, const void *sorted_samples,

@@ -182,8 +182,9 @@ def test_plan_reuse_many_calls(ds):
 
 def test_invalid_offsets_flagged(ds):
     """Bad offsets are caught on the device.  Offsets that decrease or run past n (segments
-    that would overlap or leave the array): nothing is sorted, status bit 16.  A segment longer
-    than the stated max_segment: that segment stays as it is, the others are sorted, bit 32."""
+    that would overlap or leave the array): nothing is sorted, status flag 0x10.  A segment
+    longer than the stated max_segment: that segment stays as it is, the others are sorted, flag
+    0x20."""
     n = 200_000
     keys = synth.uniform_u32(n, 77)
     plan = ds.Plan(1, False, n, max_segments=4)
