@@ -44,6 +44,7 @@ struct Geom {
     // level 2
     uint32_t L2 = 0, s2 = 0, m2max = 0, tiles2max = 0;
     uint32_t final_buckets = 0;
+    uint32_t plan_rule = 0;  // which rule chose (s1, s2): 0 preferred, 1 smallest feasible
 
     // workspace byte offsets
     size_t o_status = 0, o_wkeys = 0, o_wvals = 0;

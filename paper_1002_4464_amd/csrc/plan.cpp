@@ -121,24 +121,35 @@ int make_geom(int key_type, bool values, uint64_t n, const dsort_tuning_t &tu, G
         if (!is_pow2(L2) || L2 < c.tile_e || L2 > c.tile_max) return DSORT_E_UNSUPPORTED;
         if (tu.samples2 && (!is_pow2(tu.samples2) || tu.samples2 > L2 || tu.samples2 > kMaxSamples))
             return DSORT_E_UNSUPPORTED;
-        bool found = false;
-        const uint64_t lo = tu.samples ? tu.samples : 2;
+        // Untuned choices prefer (measured at 2^25 to 2^28, 32-bit keys with and without values:
+        // up to 5 % faster than the smallest feasible s1 and s2) s1 >= n / 2^19, capped at 256
+        // (about 32 level-2 sublists per level-1 bucket; more samples, e.g. s1 = 512 at 2^28,
+        // cost more in Steps 4-7 than they save), and s2 >= n / (4096 s1), capped at 128 (final
+        // buckets of about 4K items, eight merge passes), as long as the level-2 samples still
+        // fit one workgroup.  Where no s1 allows that, the smallest feasible s1 and s2.  Under
+        // each of the two rules s1 and s2 only grow with n (the workspace walk of dsort_plan
+        // relies on that; the rule is part of its piece key).
         const uint64_t hi = tu.samples ? tu.samples : (L1 / 8 < kMaxSamples ? L1 / 8 : kMaxSamples);
-        for (uint64_t s = lo; s <= hi && !found; s <<= 1) {
-            const uint64_t b1 = bucket_bound(m1, L1, s);
-            const uint64_t mm = ceil_div(b1, L2);
-            if (mm > kMaxPieces) continue;
-            const uint64_t t_lo = tu.samples2 ? tu.samples2 : 1;
-            const uint64_t t_hi = tu.samples2 ? tu.samples2 : (L2 < kMaxSamples ? L2 : kMaxSamples);
-            for (uint64_t t = t_lo; t <= t_hi; t <<= 1) {
-                if (mm * (2 * L2 / t - 1) <= c.final_cap) {
-                    if (mm * t <= c.samp_cap) {
-                        s1 = s; s2 = t; m2max = mm; found = true;
-                    }
-                    break;
-                }
+        const uint64_t t_lo = tu.samples2 ? tu.samples2 : 1;
+        const uint64_t t_hi = tu.samples2 ? tu.samples2 : (L2 < kMaxSamples ? L2 : kMaxSamples);
+        auto search = [&](bool pref) {
+            uint64_t p1 = 2;
+            while (pref && p1 < 256 && p1 < (n >> 19)) p1 <<= 1;
+            for (uint64_t s = tu.samples ? tu.samples : p1; s <= hi; s <<= 1) {
+                const uint64_t mm = ceil_div(bucket_bound(m1, L1, s), L2);
+                if (mm > kMaxPieces) continue;
+                uint64_t t = t_lo;  // smallest s2 whose buckets fit one workgroup
+                while (t <= t_hi && mm * (2 * L2 / t - 1) > c.final_cap) t <<= 1;
+                if (t > t_hi) continue;
+                if (pref && !tu.samples2)
+                    while (t < 128 && t < t_hi && t * s * 4096 < n) t <<= 1;
+                if (mm * t > c.samp_cap) continue;
+                s1 = s; s2 = t; m2max = mm;
+                return true;
             }
-        }
+            return false;
+        };
+        const bool found = search(true) || (g.plan_rule = 1, search(false));
         if (!found) return DSORT_E_UNSUPPORTED;
     }
 
@@ -407,16 +418,16 @@ int dsort_plan(dsort_plan_t *out, int key_type, int with_values, uint64_t max_it
     dsort_tuning_t tu{};
     if (tuning) tu = *tuning;
     // The workspace must serve every n <= max_items.  The geometry is piecewise in n: on each
-    // interval where (levels, s1, s2, sample-sort and scan variants) stay fixed, every buffer
-    // grows with n, and these pieces never recur once left (s1, s2 and the level count only
-    // grow with n).  So the largest footprint is at the right end of some piece; walk the
+    // interval where (levels, rule, s1, s2, sample-sort and scan variants) stay fixed, every
+    // buffer grows with n, and these pieces never recur once left (the level count and the
+    // rule only grow with n, and so do s1 and s2 under one rule).  So the largest footprint is at the right end of some piece; walk the
     // pieces, finding each right end by bisection.
     size_t ws = 256;
     if (max_items >= 2) {
         auto key = [](const Geom &h) {
-            return ((uint64_t)(h.levels + 1) << 56) ^ ((uint64_t)h.s1 << 36) ^
-                   ((uint64_t)h.s2 << 12) ^ ((uint64_t)h.samp_global << 1) ^
-                   (uint64_t)h.scan_large;
+            return ((uint64_t)(h.levels + 1) << 56) ^ ((uint64_t)h.plan_rule << 52) ^
+                   ((uint64_t)h.s1 << 36) ^ ((uint64_t)h.s2 << 12) ^
+                   ((uint64_t)h.samp_global << 1) ^ (uint64_t)h.scan_large;
         };
         uint64_t lo = 2;
         while (lo <= max_items) {
