@@ -217,7 +217,8 @@ int dsort_get_seg_tuning(dsort_plan_t plan, dsort_seg_tuning_t *out);
  * Each run copies the batch (d_keys, d_values: left unchanged) into the caller's scratch
  * buffers (n keys, and n values for key/value plans) and sorts there, `repeats` times (at least
  * 1), timed with HIP events on `stream`.  Blocks until done.  Arguments as for dsort_segmented.
- * On success *out (may be NULL) receives the tuning. */
+ * On success *out (may be NULL) receives the tuning; when the defaults win they are installed
+ * as an explicit tuning with their (L, s) per class (no classes when no segment is long). */
 int dsort_autotune_segmented(dsort_plan_t plan, const void *d_keys, const uint32_t *d_values,
                              uint64_t n, const uint64_t *d_offsets, uint64_t num_segments,
                              uint64_t max_segment, void *d_scratch_keys,

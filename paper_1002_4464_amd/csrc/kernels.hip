@@ -233,6 +233,54 @@ template <class T, int E> __device__ __forceinline__ void reg_sort(T (&x)[E]) {
                         cmpx(x[i + j], x[i + j + k]);
 }
 
+// In-register merges of the sorted 16-item runs of 2, 4 and 8 neighbouring lanes into sorted
+// runs of 32, 64 and 128 items (32-bit elements): Batcher's bitonic merge, the first half of it
+// as compare-exchanges between lanes -- the partner's item comes through a DPP lane
+// permutation, the lower lane keeps the minimum and the upper the maximum; the first stage of
+// each merge pairs item e with the partner's item 15 - e, which merges two ascending runs
+// without reversing one -- and its last four stages inside the lane.
+template <int CTRL, bool REV>
+__device__ __forceinline__ void dpp_cross(uint32_t (&x)[16], bool upper) {
+    uint32_t y[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const uint32_t p =
+            (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x[REV ? 15 - e : e], CTRL, 0xF, 0xF, false);
+        y[e] = upper ? max(x[e], p) : min(x[e], p);
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) x[e] = y[e];
+}
+
+__device__ __forceinline__ void inlane_bitonic(uint32_t (&x)[16]) {
+#pragma unroll
+    for (int d = 8; d >= 1; d >>= 1)
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            if ((e & d) == 0) {
+                const uint32_t a = x[e], b = x[e | d];
+                x[e] = min(a, b);
+                x[e | d] = max(a, b);
+            }
+}
+
+// DPP controls: quad_perm [1,0,3,2], [3,2,1,0], [2,3,0,1] and row_half_mirror (lane i of
+// each 8 reads lane 7 - i).
+constexpr int kDppSwap1 = 0xB1, kDppRev4 = 0x1B, kDppSwap2 = 0x4E, kDppRev8 = 0x141;
+
+__device__ __forceinline__ void dpp_merge_128(uint32_t (&x)[16]) {
+    const uint32_t lane = threadIdx.x & 63;
+    dpp_cross<kDppSwap1, true>(x, lane & 1);
+    inlane_bitonic(x);
+    dpp_cross<kDppRev4, true>(x, lane & 2);
+    dpp_cross<kDppSwap1, false>(x, lane & 1);
+    inlane_bitonic(x);
+    dpp_cross<kDppRev8, true>(x, lane & 4);
+    dpp_cross<kDppSwap2, false>(x, lane & 2);
+    dpp_cross<kDppSwap1, false>(x, lane & 1);
+    inlane_bitonic(x);
+}
+
 // Byte offset of padded LDS element i: (i + (i >> shift)) << log2(sizeof(T)) as one
 // v_add_lshl_u32 (the compiler otherwise splits the scaling into three instructions).
 template <class T> struct SizeLog2;
@@ -335,22 +383,28 @@ __device__ __forceinline__ void serial_merge(const T *lds, uint32_t ai, uint32_t
 // lds_elems(P) + 1 elements, the last one only ever read speculatively).  Thread t owns
 // items [tE, tE+E): a register network sorts them, then merge passes double the sorted run
 // length (runs of E * 2^lv items); when P / E is not a power of two the last run of a pass is
-// shorter (or has no partner).
+// shorter (or has no partner).  32-bit elements with E = 16 and P a multiple of 128 merge
+// their first three passes in registers across lanes (dpp_merge_128).
 // All threads of the block must call it.  COMP: see MergeLess (the register network always
 // compares whole elements; only the merges may compare keys alone).
 template <class T, int E, bool COMP = false>
 __device__ __forceinline__ void block_sort(T *lds, uint32_t P) {
     const uint32_t t = threadIdx.x;
     const bool act = t * E < P;
+    // whole 8-lane groups: every lane whose partners it reads is active with it
+    const bool dpp = sizeof(T) == 4 && E == 16 && P % 128 == 0;
     T x[E];
     if (act) {
 #pragma unroll
         for (int k = 0; k < E; ++k) x[k] = lds[pidx<T>(t * E + k)];
         reg_sort<T, E>(x);
+        if constexpr (sizeof(T) == 4 && E == 16)
+            if (dpp) dpp_merge_128(x);
 #pragma unroll
         for (int k = 0; k < E; ++k) lds[pidx<T>(t * E + k)] = x[k];
     }
-    for (uint32_t R = E, pair = 2; R < P; R <<= 1, pair <<= 1) {
+    const uint32_t R0 = dpp ? 8 * E : E;
+    for (uint32_t R = R0, pair = 2 * R0 / E; R < P; R <<= 1, pair <<= 1) {
         __syncthreads();
         if (act) {
             const uint32_t start = t * E;
@@ -1173,7 +1227,10 @@ __global__ __launch_bounds__((CAP / GatherE<K, V, CAP>::E), (GatherE<K, V, CAP>:
         }
         if (tid == 0) bnd[np] = total;
         __syncthreads();
-        const uint32_t P = (total + E - 1) / E * E;
+        // padded to whole runs of the block sort's first pass (128 items where it merges in
+        // registers first, else E)
+        constexpr uint32_t PR = (sizeof(T) == 4 && E == 16) ? 128 : E;
+        const uint32_t P = (total + PR - 1) / PR * PR;
         const uint32_t span = ((P + nw - 1) / nw + 63) & ~63u;
         const uint32_t x_begin = w * span, x_end = min(P, x_begin + span);
         if (x_begin < x_end) {

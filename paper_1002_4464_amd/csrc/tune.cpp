@@ -163,6 +163,16 @@ extern "C" int dsort_autotune_segmented(dsort_plan_t plan, const void *d_keys,
     } else {
         best = best_one;
     }
+    if (best.classes == 0 && g0.nclasses) {
+        // the defaults measured fastest: install them as an explicit tuning, so that the
+        // caller sees the (L, s) per class that won
+        best.classes = g0.nclasses;
+        for (uint32_t q = 0; q < g0.nclasses; ++q) {
+            best.upper[q] = q + 1 == g0.nclasses ? ~0ull : g0.cls[q].hi;
+            best.L[q] = g0.cls[q].L;
+            best.s[q] = g0.cls[q].s;
+        }
+    }
     rc = plan_set_seg_tuning(plan, best);
     if (rc != DSORT_OK) return rc;
     if (out) {
