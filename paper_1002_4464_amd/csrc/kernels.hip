@@ -384,17 +384,19 @@ __device__ __forceinline__ void serial_merge(const T *lds, uint32_t ai, uint32_t
 // items [tE, tE+E): a register network sorts them, then merge passes double the sorted run
 // length (runs of E * 2^lv items); when P / E is not a power of two the last run of a pass is
 // shorter (or has no partner).  32-bit elements with E = 16 and P a multiple of 128 merge
-// their first three passes in registers across lanes (dpp_merge_128).
+// their first three passes in registers across lanes (dpp_merge_128).  R0 > E: lds already
+// holds sorted runs of R0 items (R0 a power of two times E), so sorting starts with the
+// merge pass of those runs.
 // All threads of the block must call it.  COMP: see MergeLess (the register network always
 // compares whole elements; only the merges may compare keys alone).
 template <class T, int E, bool COMP = false>
-__device__ __forceinline__ void block_sort(T *lds, uint32_t P) {
+__device__ __forceinline__ void block_sort(T *lds, uint32_t P, uint32_t R0 = E) {
     const uint32_t t = threadIdx.x;
     const bool act = t * E < P;
     // whole 8-lane groups: every lane whose partners it reads is active with it
-    const bool dpp = sizeof(T) == 4 && E == 16 && P % 128 == 0;
+    const bool dpp = R0 <= E && sizeof(T) == 4 && E == 16 && P % 128 == 0;
     T x[E];
-    if (act) {
+    if (R0 <= E && act) {
 #pragma unroll
         for (int k = 0; k < E; ++k) x[k] = lds[pidx<T>(t * E + k)];
         reg_sort<T, E>(x);
@@ -403,8 +405,8 @@ __device__ __forceinline__ void block_sort(T *lds, uint32_t P) {
 #pragma unroll
         for (int k = 0; k < E; ++k) lds[pidx<T>(t * E + k)] = x[k];
     }
-    const uint32_t R0 = dpp ? 8 * E : E;
-    for (uint32_t R = R0, pair = 2 * R0 / E; R < P; R <<= 1, pair <<= 1) {
+    const uint32_t Rs = R0 > E ? R0 : dpp ? 8 * E : E;
+    for (uint32_t R = Rs, pair = 2 * Rs / E; R < P; R <<= 1, pair <<= 1) {
         __syncthreads();
         if (act) {
             const uint32_t start = t * E;
@@ -735,7 +737,10 @@ __global__ __launch_bounds__(CAP / E) void k_sort_samples(const SC *src, SC *dst
     for (uint32_t i = tid; i < P; i += blockDim.x)
         lds[pidx<SC>(i)] = i < count ? src[begin + i] : MaxOf<SC>::get();
     __syncthreads();
-    block_sort<SC, E, true>(lds, P);  // sample composites are in position order
+    // Each sublist's s samples are already in order (they come from its sorted items) and
+    // every range starts on a row, so the sort starts from runs of s; sample composites are
+    // in position order.
+    block_sort<SC, E, true>(lds, P, s > (uint32_t)E ? s : (uint32_t)E);
     for (uint32_t i = tid; i < count; i += blockDim.x) dst[begin + i] = lds[pidx<SC>(i)];
 }
 
@@ -809,10 +814,50 @@ __global__ __launch_bounds__(CAP / E) void k_merge_round(const SC *src, SC *dst,
 // coalesced loads and a ballot counts those <= g_j, the loads of the whole batch in flight
 // together (chunks shared by neighbouring samples come from cache).  Larger chunks are
 // bisected in global memory, one probe per step.  Pads (x >= count) are key-max items.
-#ifndef DSORT_RANK_BATCH
-#define DSORT_RANK_BATCH 8
-#endif
-constexpr uint32_t kRankBatch = DSORT_RANK_BATCH;
+constexpr uint32_t kRankBatch = 8;
+
+// The chunk counts of k_rank for chunks of at most 64 NQ items: each wave takes kRankBatch
+// global samples at a time (their chunks are wave-uniform), loads all their chunks, then counts.
+template <class K, bool V, int NQ>
+__device__ __forceinline__ void rank_chunks(const K *keys, const typename Tr<K, V>::SC *S,
+                                            uint32_t m, const uint32_t *chunk, uint32_t *rk,
+                                            uint32_t s, uint32_t w, uint32_t base,
+                                            uint32_t count, uint32_t p0) {
+    using R = Tr<K, V>;
+    using SC = typename R::SC;
+    const uint32_t lane = threadIdx.x & 63, nwv = blockDim.x >> 6;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (uint32_t j0 = wv * kRankBatch; j0 < s; j0 += nwv * kRankBatch) {
+        K v[kRankBatch][NQ];
+        uint32_t cc[kRankBatch];  // wave-uniform chunk of each global sample of the batch
+#pragma unroll
+        for (uint32_t u = 0; u < kRankBatch; ++u)
+            cc[u] = j0 + u < s ? __builtin_amdgcn_readfirstlane(chunk[j0 + u]) : s;
+#pragma unroll
+        for (uint32_t u = 0; u < kRankBatch; ++u) {
+            const uint32_t c = cc[u];
+#pragma unroll
+            for (uint32_t q = 0; q < NQ; ++q) {
+                const uint32_t y = q * 64 + lane, x = c * w + y;  // item of the sublist
+                v[u][q] = (c < s && y < w && x < count) ? keys[base + x] : KeyMax<K>::v;
+            }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kRankBatch; ++u) {
+            const uint32_t j = j0 + u, c = cc[u];
+            if (c >= s) continue;
+            const SC g = S[(size_t)(j + 1) * m - 1];
+            uint32_t le = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < NQ; ++q) {
+                const uint32_t y = q * 64 + lane;
+                const bool in = y < w && !lt(g, R::samp(v[u][q], p0 + c * w + y));
+                le += (uint32_t)__popcll(__ballot(in));
+            }
+            if (lane == 0) rk[j + 1] = c * w + le;
+        }
+    }
+}
 
 template <class K, bool V>
 __global__ __launch_bounds__(256) void k_rank(const K *keys, const void *sorted_samples,
@@ -844,39 +889,10 @@ __global__ __launch_bounds__(256) void k_rank(const K *keys, const void *sorted_
     }
     if (threadIdx.x == 0) rk[0] = 0;
     __syncthreads();
-    if (w <= 128) {
-        const uint32_t lane = threadIdx.x & 63, nwv = blockDim.x >> 6;
-        const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        for (uint32_t j0 = wv * kRankBatch; j0 < s; j0 += nwv * kRankBatch) {
-            K v[kRankBatch][2];
-            uint32_t cc[kRankBatch];  // wave-uniform chunk of each global sample of the batch
-#pragma unroll
-            for (uint32_t u = 0; u < kRankBatch; ++u)
-                cc[u] = j0 + u < s ? __builtin_amdgcn_readfirstlane(chunk[j0 + u]) : s;
-#pragma unroll
-            for (uint32_t u = 0; u < kRankBatch; ++u) {
-                const uint32_t c = cc[u];
-#pragma unroll
-                for (uint32_t q = 0; q < 2; ++q) {
-                    const uint32_t y = q * 64 + lane, x = c * w + y;  // item of the sublist
-                    v[u][q] = (c < s && y < w && x < count) ? keys[base + x] : KeyMax<K>::v;
-                }
-            }
-#pragma unroll
-            for (uint32_t u = 0; u < kRankBatch; ++u) {
-                const uint32_t j = j0 + u, c = cc[u];
-                if (c >= s) continue;
-                const SC g = S[(size_t)(j + 1) * loc.m - 1];
-                uint32_t le = 0;
-#pragma unroll
-                for (uint32_t q = 0; q < 2; ++q) {
-                    const uint32_t y = q * 64 + lane;
-                    const bool in = y < w && !lt(g, R::samp(v[u][q], p0 + c * w + y));
-                    le += (uint32_t)__popcll(__ballot(in));
-                }
-                if (lane == 0) rk[j + 1] = c * w + le;
-            }
-        }
+    if (w <= 64) {
+        rank_chunks<K, V, 1>(keys, S, loc.m, chunk, rk, s, w, base, count, p0);
+    } else if (w <= 128) {
+        rank_chunks<K, V, 2>(keys, S, loc.m, chunk, rk, s, w, base, count, p0);
     } else {
         for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) {
             const uint32_t c = chunk[j];
