@@ -350,3 +350,44 @@ def test_autotune_installs_and_keeps_input(ds):
     out, _, _ = gpu_segmented(ds, keys, offs, plan=plan, max_segment=int(sizes.max()))
     want, _ = oracle.segmented_sort(keys, offs)
     assert (out == want).all()
+
+
+def test_concurrent_calls_from_two_threads(ds):
+    """Segmented calls from two host threads, each on its own plan and stream, at the same
+    time: the bucket size classes of both share the library's side streams, and every result
+    must still be the oracle's (the fork and join of a call are enqueued under one lock)."""
+    import threading
+    import torch
+    sizes = synth.segment_sizes(120, 71, 6, 18)
+    offs, n = offsets_of(sizes)
+    inputs = [synth.uniform_u32(n, 300 + i) for i in range(6)]
+    wants = [oracle.segmented_sort(x, offs)[0] for x in inputs]
+    errors = []
+
+    def worker(tid):
+        try:
+            st = torch.cuda.Stream()
+            plan = ds.Plan(1, False, n, max_segments=sizes.size)
+            ws = plan.workspace("cuda")
+            with torch.cuda.stream(st):
+                to = torch.from_numpy(offs.copy()).cuda()
+            for rep in range(3):
+                i = 2 * rep + tid
+                with torch.cuda.stream(st):
+                    tk = to_dev(inputs[i])
+                    plan.sort_segmented(tk, to, max_segment=int(sizes.max()), workspace=ws,
+                                        stream=st)
+                st.synchronize()
+                if not (from_dev(tk, np.uint32) == wants[i]).all():
+                    errors.append(f"thread {tid} input {i}")
+        except Exception as e:  # reported below, in the test's thread
+            errors.append(f"thread {tid}: {e!r}")
+
+    say("[seg] two host threads, 3 calls each, n =", n)
+    ts = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in ts), "a worker thread did not finish"
+    assert not errors, errors
