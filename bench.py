@@ -34,9 +34,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak: one wave64 VALU instruction per CU per clock (four SIMDs of 16 lanes, each
+# taking four clocks per wave instruction), 256 CUs at 2.4 GHz.
+VALU_PEAK_G = 256 * 2.4
 METRIC = "Mkeys/s + HBM GB/s (2^28 u32); p50/p99 latency, batched/served vs plain sort"
 KERNEL_SRC = os.path.join(ROOT, "paper_1002_4464_amd", "csrc", "kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu.json")
 
 
 def log(*a):
@@ -90,6 +94,20 @@ def traffic_for(stage: str):
     if t.get("kernel_source_sha256_16") != kernel_hash():
         return None
     v = t.get("bytes_per_step", {}).get(stage)
+    return float(v) if v is not None else None
+
+
+def valu_for(stage: str):
+    """VALU wave instructions per step of a stage group (rocprofv3 SQ_INSTS_VALU), if
+    recorded for the current kernel source."""
+    try:
+        with open(VALU_FILE) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    v = t.get("valu_wave_instr_per_step", {}).get(stage)
     return float(v) if v is not None else None
 
 
@@ -510,6 +528,33 @@ def ingest_pmc(fetch_csv: str, write_csv: str, copy_bytes: int, sorts: int, out_
     print(json.dumps(rec, indent=1, sort_keys=True))
 
 
+def ingest_valu(csv_path: str, sorts: int, out_json: str):
+    """Turns a rocprofv3 --pmc run that holds SQ_INSTS_VALU into VALU wave instructions per sort
+    for each stage group (profiles/valu.json), for the issue-bound view of the roofline."""
+    import csv
+    import collections
+    rows = [r for r in csv.DictReader(open(csv_path)) if r["Counter_Name"] == "SQ_INSTS_VALU"]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    per = collections.defaultdict(float)
+    seen = {}
+    started = False
+    for r in rows:
+        name = r["Kernel_Name"]
+        if "dsort" not in name:
+            continue
+        grp = _group_of(name, seen)
+        if grp == "init":
+            started = True
+            continue
+        if started:
+            per[grp] += float(r["Counter_Value"])
+    rec = {"kernel_source_sha256_16": kernel_hash(), "sorts": sorts,
+           "valu_wave_instr_per_step": {k: v / sorts for k, v in per.items()}}
+    with open(out_json, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    print(json.dumps(rec, indent=1, sort_keys=True))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -526,6 +571,9 @@ def main():
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 counter CSVs of a --copy-calibration run into "
                          "profiles/traffic.json (CPU only)")
+    ap.add_argument("--ingest-valu", metavar="PMC_CSV",
+                    help="turn a rocprofv3 counter CSV holding SQ_INSTS_VALU into "
+                         "profiles/valu.json (CPU only)")
     ap.add_argument("--sorts", type=int, default=1, help="sorts in the ingested runs")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
     ap.add_argument("--batched-segments", type=int, default=4096)
@@ -546,6 +594,9 @@ def main():
     if args.ingest_pmc:
         ingest_pmc(args.ingest_pmc[0], args.ingest_pmc[1], args.copy_calibration, args.sorts,
                    TRAFFIC_FILE)
+        return
+    if args.ingest_valu:
+        ingest_valu(args.ingest_valu, args.sorts, VALU_FILE)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -642,7 +693,17 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom),
                     "algorithmic_bytes": alg, "ms_per_step": round(t_ms, 4),
                     "launches_per_step": sum(stages[nm][1] for nm in STAGE_GROUPS[dom]
-                                             if nm in stages) // K}
+                                             if nm in stages) // K,
+                    "alu": None}
+        # The same kernels against their instruction-issue bound: VALU wave instructions per
+        # step (counted by rocprofv3 on this kernel source) over the live kernel time.
+        vi = valu_for(dom)
+        if vi:
+            ach = vi / (t_ms * 1e-3) / 1e9
+            roofline["alu"] = {"bound": "alu", "achieved": round(ach, 1), "peak": VALU_PEAK_G,
+                               "unit": "G VALU wave instructions/s",
+                               "frac": round(ach / VALU_PEAK_G, 4),
+                               "valu_wave_instructions": vi}
     del bufs
     batched = None
     if not args.no_batched:
