@@ -239,18 +239,92 @@ template <class T, int E> __device__ __forceinline__ void reg_sort(T (&x)[E]) {
 // permutation, the lower lane keeps the minimum and the upper the maximum; the first stage of
 // each merge pairs item e with the partner's item 15 - e, which merges two ascending runs
 // without reversing one -- and its last four stages inside the lane.
+
+// Eight compare-exchanges of one cross-lane stage: per item, v_sub_co_u32 with the partner's
+// item as its DPP operand sets VCC where the partner's item is the smaller, s_xor flips that
+// on the lanes that keep the minimum (`lower`), and v_cndmask (DPP operand again) keeps the own
+// item where VCC is set, else takes the partner's: two vector instructions instead of min,
+// max and a select.  The leading s_nop gives the DPP reads the two wait states a VGPR needs
+// after a vector write.
+#define DS_XITEM(J, CTRL)                                                                   \
+    "v_sub_co_u32_dpp %[t], vcc, %[s" #J "], %[x" #J "] " CTRL                             \
+    " row_mask:0xf bank_mask:0xf\n\t"                                                       \
+    "s_xor_b64 vcc, vcc, %[m]\n\t"                                                          \
+    "v_cndmask_b32_dpp %[y" #J "], %[s" #J "], %[x" #J "], vcc " CTRL                      \
+    " row_mask:0xf bank_mask:0xf\n\t"
+#define DS_XCROSS8(CTRL)                                                                    \
+    asm("s_nop 1\n\t" DS_XITEM(0, CTRL) DS_XITEM(1, CTRL) DS_XITEM(2, CTRL) DS_XITEM(3, CTRL) \
+            DS_XITEM(4, CTRL) DS_XITEM(5, CTRL) DS_XITEM(6, CTRL) DS_XITEM(7, CTRL)         \
+        : [y0] "=&v"(y[e0]), [y1] "=&v"(y[e0 + 1]), [y2] "=&v"(y[e0 + 2]),                 \
+          [y3] "=&v"(y[e0 + 3]), [y4] "=&v"(y[e0 + 4]), [y5] "=&v"(y[e0 + 5]),             \
+          [y6] "=&v"(y[e0 + 6]), [y7] "=&v"(y[e0 + 7]), [t] "=&v"(tmp)                     \
+        : [s0] "v"(x[src(e0)]), [s1] "v"(x[src(e0 + 1)]), [s2] "v"(x[src(e0 + 2)]),        \
+          [s3] "v"(x[src(e0 + 3)]), [s4] "v"(x[src(e0 + 4)]), [s5] "v"(x[src(e0 + 5)]),    \
+          [s6] "v"(x[src(e0 + 6)]), [s7] "v"(x[src(e0 + 7)]), [x0] "v"(x[e0]),             \
+          [x1] "v"(x[e0 + 1]), [x2] "v"(x[e0 + 2]), [x3] "v"(x[e0 + 3]), [x4] "v"(x[e0 + 4]), \
+          [x5] "v"(x[e0 + 5]), [x6] "v"(x[e0 + 6]), [x7] "v"(x[e0 + 7]), [m] "s"(lower)    \
+        : "vcc")
+
+// The partner's item comes through a DPP lane permutation (CTRL); the lower lane of each pair
+// keeps the minimum and the upper the maximum.  REV pairs item e with the partner's item 15 - e.
 template <int CTRL, bool REV>
-__device__ __forceinline__ void dpp_cross(uint32_t (&x)[16], bool upper) {
+__device__ __forceinline__ void dpp_cross(uint32_t (&x)[16], uint64_t lower) {
+    constexpr auto src = [](int e) { return REV ? 15 - e : e; };
+    uint32_t y[16], tmp;
+#pragma unroll
+    for (int e0 = 0; e0 < 16; e0 += 8) {
+        if constexpr (CTRL == 0xB1) DS_XCROSS8("quad_perm:[1,0,3,2]");
+        else if constexpr (CTRL == 0x1B) DS_XCROSS8("quad_perm:[3,2,1,0]");
+        else if constexpr (CTRL == 0x4E) DS_XCROSS8("quad_perm:[2,3,0,1]");
+        else DS_XCROSS8("row_half_mirror");
+    }
+    (void)tmp;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) x[e] = y[e];
+}
+#undef DS_XCROSS8
+#undef DS_XITEM
+
+// Cross-lane stages whose minimum-keeping lanes fill whole DPP banks (groups of four lanes of
+// a row): v_min writes those banks (bank mask LO) and v_max the others (HI), each reading the
+// partner's item as its DPP operand (controls CL / CH), so the stage costs two vector
+// instructions per item and no mask.  KIND 0: lane i of 8 against lane 7 - i (row_half_mirror),
+// item e against item 15 - e; KIND 1: the same over 16 lanes (row_mirror); KIND 2: lane i
+// against lane i ^ 4, item e against item e (the rotations by 12 and 4 lanes of a row bring
+// lane i + 4 to the lower lanes and lane i - 4 to the upper ones).
+#define DS_BITEM(J, CL, CH, LO, HI)                                                          \
+    "v_min_u32_dpp %[y" #J "], %[s" #J "], %[x" #J "] " CL " row_mask:0xf bank_mask:" LO   \
+    "\n\t"                                                                                   \
+    "v_max_u32_dpp %[y" #J "], %[s" #J "], %[x" #J "] " CH " row_mask:0xf bank_mask:" HI   \
+    "\n\t"
+#define DS_BCROSS8(CL, CH, LO, HI)                                                            \
+    asm("s_nop 1\n\t" DS_BITEM(0, CL, CH, LO, HI) DS_BITEM(1, CL, CH, LO, HI)                \
+            DS_BITEM(2, CL, CH, LO, HI) DS_BITEM(3, CL, CH, LO, HI) DS_BITEM(4, CL, CH, LO, HI) \
+                DS_BITEM(5, CL, CH, LO, HI) DS_BITEM(6, CL, CH, LO, HI)                       \
+                    DS_BITEM(7, CL, CH, LO, HI)                                               \
+        : [y0] "=&v"(y[e0]), [y1] "=&v"(y[e0 + 1]), [y2] "=&v"(y[e0 + 2]),                   \
+          [y3] "=&v"(y[e0 + 3]), [y4] "=&v"(y[e0 + 4]), [y5] "=&v"(y[e0 + 5]),               \
+          [y6] "=&v"(y[e0 + 6]), [y7] "=&v"(y[e0 + 7])                                       \
+        : [s0] "v"(x[src(e0)]), [s1] "v"(x[src(e0 + 1)]), [s2] "v"(x[src(e0 + 2)]),          \
+          [s3] "v"(x[src(e0 + 3)]), [s4] "v"(x[src(e0 + 4)]), [s5] "v"(x[src(e0 + 5)]),      \
+          [s6] "v"(x[src(e0 + 6)]), [s7] "v"(x[src(e0 + 7)]), [x0] "v"(x[e0]),               \
+          [x1] "v"(x[e0 + 1]), [x2] "v"(x[e0 + 2]), [x3] "v"(x[e0 + 3]), [x4] "v"(x[e0 + 4]), \
+          [x5] "v"(x[e0 + 5]), [x6] "v"(x[e0 + 6]), [x7] "v"(x[e0 + 7]))
+
+template <int KIND> __device__ __forceinline__ void dpp_cross_banks(uint32_t (&x)[16]) {
+    constexpr auto src = [](int e) { return KIND == 2 ? e : 15 - e; };
     uint32_t y[16];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const uint32_t p =
-            (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x[REV ? 15 - e : e], CTRL, 0xF, 0xF, false);
-        y[e] = upper ? max(x[e], p) : min(x[e], p);
+    for (int e0 = 0; e0 < 16; e0 += 8) {
+        if constexpr (KIND == 0) DS_BCROSS8("row_half_mirror", "row_half_mirror", "0x5", "0xa");
+        else if constexpr (KIND == 1) DS_BCROSS8("row_mirror", "row_mirror", "0x3", "0xc");
+        else DS_BCROSS8("row_ror:12", "row_ror:4", "0x5", "0xa");
     }
 #pragma unroll
     for (int e = 0; e < 16; ++e) x[e] = y[e];
 }
+#undef DS_BCROSS8
+#undef DS_BITEM
 
 __device__ __forceinline__ void inlane_bitonic(uint32_t (&x)[16]) {
 #pragma unroll
@@ -268,16 +342,28 @@ __device__ __forceinline__ void inlane_bitonic(uint32_t (&x)[16]) {
 // each 8 reads lane 7 - i).
 constexpr int kDppSwap1 = 0xB1, kDppRev4 = 0x1B, kDppSwap2 = 0x4E, kDppRev8 = 0x141;
 
+// lanes whose bit 0 or 1 is clear: the lower lane of a pair 1 or 2 lanes apart
+constexpr uint64_t kLow1 = 0x5555555555555555ull, kLow2 = 0x3333333333333333ull;
+
 __device__ __forceinline__ void dpp_merge_128(uint32_t (&x)[16]) {
-    const uint32_t lane = threadIdx.x & 63;
-    dpp_cross<kDppSwap1, true>(x, lane & 1);
+    dpp_cross<kDppSwap1, true>(x, kLow1);
     inlane_bitonic(x);
-    dpp_cross<kDppRev4, true>(x, lane & 2);
-    dpp_cross<kDppSwap1, false>(x, lane & 1);
+    dpp_cross<kDppRev4, true>(x, kLow2);
+    dpp_cross<kDppSwap1, false>(x, kLow1);
     inlane_bitonic(x);
-    dpp_cross<kDppRev8, true>(x, lane & 4);
-    dpp_cross<kDppSwap2, false>(x, lane & 2);
-    dpp_cross<kDppSwap1, false>(x, lane & 1);
+    dpp_cross_banks<0>(x);
+    dpp_cross<kDppSwap2, false>(x, kLow2);
+    dpp_cross<kDppSwap1, false>(x, kLow1);
+    inlane_bitonic(x);
+}
+
+// The next merge, of the sorted 128-item runs of the two halves of a 16-lane row into one run
+// of 256 items.
+__device__ __forceinline__ void dpp_merge_256(uint32_t (&x)[16]) {
+    dpp_cross_banks<1>(x);
+    dpp_cross_banks<2>(x);
+    dpp_cross<kDppSwap2, false>(x, kLow2);
+    dpp_cross<kDppSwap1, false>(x, kLow1);
     inlane_bitonic(x);
 }
 
@@ -339,6 +425,28 @@ __device__ __forceinline__ uint32_t merge_path(const T *lds, uint32_t a0, uint32
     return lo;
 }
 
+// The same split found with a fixed number of halving steps, top = a power of two >= na and
+// >= nb (the same for every lane, so the loop needs no exit test): the largest a in [lo, hi]
+// whose A[a - 1] does not follow B[diag - a], stepping from lo by top, top / 2, ..., 1 with
+// each probe clamped to hi (the first probe is hi itself).  Every probe reads inside A and B.
+template <class T, bool COMP = false>
+__device__ __forceinline__ uint32_t merge_split(const T *lds, uint32_t a0, uint32_t na,
+                                                uint32_t b0, uint32_t nb, uint32_t diag,
+                                                uint32_t top) {
+    const uint32_t lo = diag > nb ? diag - nb : 0, hi = min(diag, na);
+    uint32_t pos = lo;
+    if (lo < hi) {
+        const uint32_t am1 = a0 - 1, bd = b0 + diag;
+        for (uint32_t step = top; step; step >>= 1) {
+            const uint32_t q = min(pos + step, hi);
+            const T av = lds_at<T>(lds, am1 + q);
+            const T bv = lds_at<T>(lds, bd - q);
+            pos = mlt<COMP>(bv, av) ? pos : q;
+        }
+    }
+    return pos;
+}
+
 // Serial stable merge of E outputs starting at A index ai (< a_end) / B index bi (< b_end),
 // for an LDS array with one readable element past every index it can reach (so no clamp).
 template <class T, int E, bool COMP = false>
@@ -384,7 +492,8 @@ __device__ __forceinline__ void serial_merge(const T *lds, uint32_t ai, uint32_t
 // items [tE, tE+E): a register network sorts them, then merge passes double the sorted run
 // length (runs of E * 2^lv items); when P / E is not a power of two the last run of a pass is
 // shorter (or has no partner).  32-bit elements with E = 16 and P a multiple of 128 merge
-// their first three passes in registers across lanes (dpp_merge_128).  R0 > E: lds already
+// their first three passes in registers across lanes (dpp_merge_128), and the fourth too
+// when P is a multiple of 256 (dpp_merge_256).  R0 > E: lds already
 // holds sorted runs of R0 items (R0 a power of two times E), so sorting starts with the
 // merge pass of those runs.
 // All threads of the block must call it.  COMP: see MergeLess (the register network always
@@ -395,18 +504,22 @@ __device__ __forceinline__ void block_sort(T *lds, uint32_t P, uint32_t R0 = E) 
     const bool act = t * E < P;
     // whole 8-lane groups: every lane whose partners it reads is active with it
     const bool dpp = R0 <= E && sizeof(T) == 4 && E == 16 && P % 128 == 0;
+    const bool dpp16 = dpp && P % 256 == 0;  // whole 16-lane rows: one more register merge
     T x[E];
     if (R0 <= E && act) {
 #pragma unroll
         for (int k = 0; k < E; ++k) x[k] = lds[pidx<T>(t * E + k)];
         reg_sort<T, E>(x);
-        if constexpr (sizeof(T) == 4 && E == 16)
+        if constexpr (sizeof(T) == 4 && E == 16) {
             if (dpp) dpp_merge_128(x);
+            if (dpp16) dpp_merge_256(x);
+        }
 #pragma unroll
         for (int k = 0; k < E; ++k) lds[pidx<T>(t * E + k)] = x[k];
     }
-    const uint32_t Rs = R0 > E ? R0 : dpp ? 8 * E : E;
-    for (uint32_t R = Rs, pair = 2 * Rs / E; R < P; R <<= 1, pair <<= 1) {
+    const uint32_t Rs = R0 > E ? R0 : dpp16 ? 16 * E : dpp ? 8 * E : E;
+    for (uint32_t R = Rs, pair = 2 * Rs / E, top = pow2_at_least(Rs); R < P;
+         R <<= 1, pair <<= 1, top <<= 1) {
         __syncthreads();
         if (act) {
             const uint32_t start = t * E;
@@ -414,7 +527,7 @@ __device__ __forceinline__ void block_sort(T *lds, uint32_t P, uint32_t R0 = E) 
             const uint32_t diag = start - base;
             const uint32_t na = min(R, P - base);
             const uint32_t nb = min(R, P - base - na);
-            const uint32_t a = merge_path<T, COMP>(lds, base, na, base + na, nb, diag);
+            const uint32_t a = merge_split<T, COMP>(lds, base, na, base + na, nb, diag, top);
             serial_merge_nc<T, E, COMP>(lds, base + a, base + na, base + na + diag - a,
                                         base + na + nb, x);
         }
@@ -1243,9 +1356,9 @@ __global__ __launch_bounds__((CAP / GatherE<K, V, CAP>::E), (GatherE<K, V, CAP>:
         }
         if (tid == 0) bnd[np] = total;
         __syncthreads();
-        // padded to whole runs of the block sort's first pass (128 items where it merges in
+        // padded to whole runs of the block sort's first pass (256 items where it merges in
         // registers first, else E)
-        constexpr uint32_t PR = (sizeof(T) == 4 && E == 16) ? 128 : E;
+        constexpr uint32_t PR = (sizeof(T) == 4 && E == 16) ? 256 : E;
         const uint32_t P = (total + PR - 1) / PR * PR;
         const uint32_t span = ((P + nw - 1) / nw + 63) & ~63u;
         const uint32_t x_begin = w * span, x_end = min(P, x_begin + span);
