@@ -245,7 +245,7 @@ template <class T, int E> __device__ __forceinline__ void reg_sort(T (&x)[E]) {
 // on the lanes that keep the minimum (`lower`), and v_cndmask (DPP operand again) keeps the own
 // item where VCC is set, else takes the partner's: two vector instructions instead of min,
 // max and a select.  The leading s_nop gives the DPP reads the two wait states a VGPR needs
-// after a vector write.
+// after a vector write; VCC and SCC (written by s_xor) are clobbered.
 #define DS_XITEM(J, CTRL)                                                                   \
     "v_sub_co_u32_dpp %[t], vcc, %[s" #J "], %[x" #J "] " CTRL                             \
     " row_mask:0xf bank_mask:0xf\n\t"                                                       \
@@ -263,7 +263,7 @@ template <class T, int E> __device__ __forceinline__ void reg_sort(T (&x)[E]) {
           [s6] "v"(x[src(e0 + 6)]), [s7] "v"(x[src(e0 + 7)]), [x0] "v"(x[e0]),             \
           [x1] "v"(x[e0 + 1]), [x2] "v"(x[e0 + 2]), [x3] "v"(x[e0 + 3]), [x4] "v"(x[e0 + 4]), \
           [x5] "v"(x[e0 + 5]), [x6] "v"(x[e0 + 6]), [x7] "v"(x[e0 + 7]), [m] "s"(lower)    \
-        : "vcc")
+        : "vcc", "scc")
 
 // The partner's item comes through a DPP lane permutation (CTRL); the lower lane of each pair
 // keeps the minimum and the upper the maximum.  REV pairs item e with the partner's item 15 - e.
@@ -312,17 +312,50 @@ __device__ __forceinline__ void dpp_cross(uint32_t (&x)[16], uint64_t lower) {
           [x5] "v"(x[e0 + 5]), [x6] "v"(x[e0 + 6]), [x7] "v"(x[e0 + 7]))
 
 template <int KIND> __device__ __forceinline__ void dpp_cross_banks(uint32_t (&x)[16]) {
-    constexpr auto src = [](int e) { return KIND == 2 ? e : 15 - e; };
+    constexpr auto src = [](int e) { return KIND >= 2 ? e : 15 - e; };
     uint32_t y[16];
 #pragma unroll
     for (int e0 = 0; e0 < 16; e0 += 8) {
         if constexpr (KIND == 0) DS_BCROSS8("row_half_mirror", "row_half_mirror", "0x5", "0xa");
         else if constexpr (KIND == 1) DS_BCROSS8("row_mirror", "row_mirror", "0x3", "0xc");
-        else DS_BCROSS8("row_ror:12", "row_ror:4", "0x5", "0xa");
+        else if constexpr (KIND == 2) DS_BCROSS8("row_ror:12", "row_ror:4", "0x5", "0xa");
+        else DS_BCROSS8("row_ror:8", "row_ror:8", "0x3", "0xc");  // lane i ^ 8
     }
 #pragma unroll
     for (int e = 0; e < 16; ++e) x[e] = y[e];
 }
+
+// Lane i of each 32 against lane 31 - i, item e against item 15 - e: the partner's items come
+// through ds_swizzle (reversal within 32 lanes, done by the LDS crossbar, no vector
+// instruction); rows 0 and 2 keep the minimum, rows 1 and 3 the maximum (row-masked v_min and
+// v_max, the DPP control an identity).
+#define DS_RITEM(J)                                                                             \
+    "v_min_u32_dpp %[y" #J "], %[p" #J "], %[x" #J "] quad_perm:[0,1,2,3] row_mask:0x5 "        \
+    "bank_mask:0xf\n\t"                                                                         \
+    "v_max_u32_dpp %[y" #J "], %[p" #J "], %[x" #J "] quad_perm:[0,1,2,3] row_mask:0xa "        \
+    "bank_mask:0xf\n\t"
+__device__ __forceinline__ void cross_rev32(uint32_t (&x)[16]) {
+    uint32_t y[16];
+#pragma unroll
+    for (int e0 = 0; e0 < 16; e0 += 8) {
+        uint32_t p[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            p[j] = (uint32_t)__builtin_amdgcn_ds_swizzle((int)x[15 - e0 - j], 0x7C1F);
+        asm("s_nop 1\n\t" DS_RITEM(0) DS_RITEM(1) DS_RITEM(2) DS_RITEM(3) DS_RITEM(4) DS_RITEM(5)
+                DS_RITEM(6) DS_RITEM(7)
+            : [y0] "=&v"(y[e0]), [y1] "=&v"(y[e0 + 1]), [y2] "=&v"(y[e0 + 2]),
+              [y3] "=&v"(y[e0 + 3]), [y4] "=&v"(y[e0 + 4]), [y5] "=&v"(y[e0 + 5]),
+              [y6] "=&v"(y[e0 + 6]), [y7] "=&v"(y[e0 + 7])
+            : [p0] "v"(p[0]), [p1] "v"(p[1]), [p2] "v"(p[2]), [p3] "v"(p[3]), [p4] "v"(p[4]),
+              [p5] "v"(p[5]), [p6] "v"(p[6]), [p7] "v"(p[7]), [x0] "v"(x[e0]),
+              [x1] "v"(x[e0 + 1]), [x2] "v"(x[e0 + 2]), [x3] "v"(x[e0 + 3]), [x4] "v"(x[e0 + 4]),
+              [x5] "v"(x[e0 + 5]), [x6] "v"(x[e0 + 6]), [x7] "v"(x[e0 + 7]));
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) x[e] = y[e];
+}
+#undef DS_RITEM
 #undef DS_BCROSS8
 #undef DS_BITEM
 
@@ -361,6 +394,16 @@ __device__ __forceinline__ void dpp_merge_128(uint32_t (&x)[16]) {
 // of 256 items.
 __device__ __forceinline__ void dpp_merge_256(uint32_t (&x)[16]) {
     dpp_cross_banks<1>(x);
+    dpp_cross_banks<2>(x);
+    dpp_cross<kDppSwap2, false>(x, kLow2);
+    dpp_cross<kDppSwap1, false>(x, kLow1);
+    inlane_bitonic(x);
+}
+
+// And the next, of the 256-item runs of two neighbouring rows into one run of 512 items.
+__device__ __forceinline__ void dpp_merge_512(uint32_t (&x)[16]) {
+    cross_rev32(x);
+    dpp_cross_banks<3>(x);
     dpp_cross_banks<2>(x);
     dpp_cross<kDppSwap2, false>(x, kLow2);
     dpp_cross<kDppSwap1, false>(x, kLow1);
@@ -492,8 +535,9 @@ __device__ __forceinline__ void serial_merge(const T *lds, uint32_t ai, uint32_t
 // items [tE, tE+E): a register network sorts them, then merge passes double the sorted run
 // length (runs of E * 2^lv items); when P / E is not a power of two the last run of a pass is
 // shorter (or has no partner).  32-bit elements with E = 16 and P a multiple of 128 merge
-// their first three passes in registers across lanes (dpp_merge_128), and the fourth too
-// when P is a multiple of 256 (dpp_merge_256).  R0 > E: lds already
+// their first three passes in registers across lanes (dpp_merge_128), the fourth too when P
+// is a multiple of 256 (dpp_merge_256) and the fifth when it is one of 512 (dpp_merge_512).
+// R0 > E: lds already
 // holds sorted runs of R0 items (R0 a power of two times E), so sorting starts with the
 // merge pass of those runs.
 // All threads of the block must call it.  COMP: see MergeLess (the register network always
@@ -505,6 +549,7 @@ __device__ __forceinline__ void block_sort(T *lds, uint32_t P, uint32_t R0 = E) 
     // whole 8-lane groups: every lane whose partners it reads is active with it
     const bool dpp = R0 <= E && sizeof(T) == 4 && E == 16 && P % 128 == 0;
     const bool dpp16 = dpp && P % 256 == 0;  // whole 16-lane rows: one more register merge
+    const bool dpp32 = dpp && P % 512 == 0;  // whole 32-lane halves: and another
     T x[E];
     if (R0 <= E && act) {
 #pragma unroll
@@ -513,11 +558,12 @@ __device__ __forceinline__ void block_sort(T *lds, uint32_t P, uint32_t R0 = E) 
         if constexpr (sizeof(T) == 4 && E == 16) {
             if (dpp) dpp_merge_128(x);
             if (dpp16) dpp_merge_256(x);
+            if (dpp32) dpp_merge_512(x);
         }
 #pragma unroll
         for (int k = 0; k < E; ++k) lds[pidx<T>(t * E + k)] = x[k];
     }
-    const uint32_t Rs = R0 > E ? R0 : dpp16 ? 16 * E : dpp ? 8 * E : E;
+    const uint32_t Rs = R0 > E ? R0 : dpp32 ? 32 * E : dpp16 ? 16 * E : dpp ? 8 * E : E;
     for (uint32_t R = Rs, pair = 2 * Rs / E, top = pow2_at_least(Rs); R < P;
          R <<= 1, pair <<= 1, top <<= 1) {
         __syncthreads();
