@@ -325,36 +325,49 @@ template <int KIND> __device__ __forceinline__ void dpp_cross_banks(uint32_t (&x
     for (int e = 0; e < 16; ++e) x[e] = y[e];
 }
 
-// Lane i of each 32 against lane 31 - i, item e against item 15 - e: the partner's items come
-// through ds_swizzle (reversal within 32 lanes, done by the LDS crossbar, no vector
-// instruction); rows 0 and 2 keep the minimum, rows 1 and 3 the maximum (row-masked v_min and
-// v_max, the DPP control an identity).
-#define DS_RITEM(J)                                                                             \
-    "v_min_u32_dpp %[y" #J "], %[p" #J "], %[x" #J "] quad_perm:[0,1,2,3] row_mask:0x5 "        \
-    "bank_mask:0xf\n\t"                                                                         \
-    "v_max_u32_dpp %[y" #J "], %[p" #J "], %[x" #J "] quad_perm:[0,1,2,3] row_mask:0xa "        \
-    "bank_mask:0xf\n\t"
-__device__ __forceinline__ void cross_rev32(uint32_t (&x)[16]) {
+// Stages whose partner lane lies in another row of 16, the partner's items brought by the LDS
+// crossbar (no vector instruction) and the minimum kept by whole rows: row-masked v_min for
+// the rows in LO, v_max for those in HI (the DPP control an identity).  KIND 0: lane i of 32
+// against lane 31 - i, item e against item 15 - e (ds_swizzle reversal within 32 lanes, rows 0
+// and 2 keep the minimum); KIND 1: lane i of 64 against lane 63 - i, item e against 15 - e
+// (ds_bpermute; rows 0 and 1); KIND 2: lane i against lane i ^ 16, item e against item e
+// (ds_swizzle; rows 0 and 2).
+#define DS_RITEM(J, LO, HI)                                                                     \
+    "v_min_u32_dpp %[y" #J "], %[p" #J "], %[x" #J "] quad_perm:[0,1,2,3] row_mask:" LO         \
+    " bank_mask:0xf\n\t"                                                                        \
+    "v_max_u32_dpp %[y" #J "], %[p" #J "], %[x" #J "] quad_perm:[0,1,2,3] row_mask:" HI         \
+    " bank_mask:0xf\n\t"
+#define DS_RCROSS8(LO, HI)                                                                      \
+    asm("s_nop 1\n\t" DS_RITEM(0, LO, HI) DS_RITEM(1, LO, HI) DS_RITEM(2, LO, HI)               \
+            DS_RITEM(3, LO, HI) DS_RITEM(4, LO, HI) DS_RITEM(5, LO, HI) DS_RITEM(6, LO, HI)     \
+                DS_RITEM(7, LO, HI)                                                             \
+        : [y0] "=&v"(y[e0]), [y1] "=&v"(y[e0 + 1]), [y2] "=&v"(y[e0 + 2]),                     \
+          [y3] "=&v"(y[e0 + 3]), [y4] "=&v"(y[e0 + 4]), [y5] "=&v"(y[e0 + 5]),                 \
+          [y6] "=&v"(y[e0 + 6]), [y7] "=&v"(y[e0 + 7])                                         \
+        : [p0] "v"(p[0]), [p1] "v"(p[1]), [p2] "v"(p[2]), [p3] "v"(p[3]), [p4] "v"(p[4]),      \
+          [p5] "v"(p[5]), [p6] "v"(p[6]), [p7] "v"(p[7]), [x0] "v"(x[e0]),                     \
+          [x1] "v"(x[e0 + 1]), [x2] "v"(x[e0 + 2]), [x3] "v"(x[e0 + 3]), [x4] "v"(x[e0 + 4]),   \
+          [x5] "v"(x[e0 + 5]), [x6] "v"(x[e0 + 6]), [x7] "v"(x[e0 + 7]))
+template <int KIND> __device__ __forceinline__ void cross_rows(uint32_t (&x)[16]) {
+    const int rev_addr = (int)(63 - (threadIdx.x & 63)) * 4;  // ds_bpermute source lane, bytes
     uint32_t y[16];
 #pragma unroll
     for (int e0 = 0; e0 < 16; e0 += 8) {
         uint32_t p[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-            p[j] = (uint32_t)__builtin_amdgcn_ds_swizzle((int)x[15 - e0 - j], 0x7C1F);
-        asm("s_nop 1\n\t" DS_RITEM(0) DS_RITEM(1) DS_RITEM(2) DS_RITEM(3) DS_RITEM(4) DS_RITEM(5)
-                DS_RITEM(6) DS_RITEM(7)
-            : [y0] "=&v"(y[e0]), [y1] "=&v"(y[e0 + 1]), [y2] "=&v"(y[e0 + 2]),
-              [y3] "=&v"(y[e0 + 3]), [y4] "=&v"(y[e0 + 4]), [y5] "=&v"(y[e0 + 5]),
-              [y6] "=&v"(y[e0 + 6]), [y7] "=&v"(y[e0 + 7])
-            : [p0] "v"(p[0]), [p1] "v"(p[1]), [p2] "v"(p[2]), [p3] "v"(p[3]), [p4] "v"(p[4]),
-              [p5] "v"(p[5]), [p6] "v"(p[6]), [p7] "v"(p[7]), [x0] "v"(x[e0]),
-              [x1] "v"(x[e0 + 1]), [x2] "v"(x[e0 + 2]), [x3] "v"(x[e0 + 3]), [x4] "v"(x[e0 + 4]),
-              [x5] "v"(x[e0 + 5]), [x6] "v"(x[e0 + 6]), [x7] "v"(x[e0 + 7]));
+        for (int j = 0; j < 8; ++j) {
+            const int v = (int)x[KIND == 2 ? e0 + j : 15 - e0 - j];
+            p[j] = (uint32_t)(KIND == 0   ? __builtin_amdgcn_ds_swizzle(v, 0x7C1F)
+                              : KIND == 1 ? __builtin_amdgcn_ds_bpermute(rev_addr, v)
+                                          : __builtin_amdgcn_ds_swizzle(v, 0x401F));
+        }
+        if constexpr (KIND == 1) DS_RCROSS8("0x3", "0xc");
+        else DS_RCROSS8("0x5", "0xa");
     }
 #pragma unroll
     for (int e = 0; e < 16; ++e) x[e] = y[e];
 }
+#undef DS_RCROSS8
 #undef DS_RITEM
 #undef DS_BCROSS8
 #undef DS_BITEM
@@ -402,7 +415,18 @@ __device__ __forceinline__ void dpp_merge_256(uint32_t (&x)[16]) {
 
 // And the next, of the 256-item runs of two neighbouring rows into one run of 512 items.
 __device__ __forceinline__ void dpp_merge_512(uint32_t (&x)[16]) {
-    cross_rev32(x);
+    cross_rows<0>(x);
+    dpp_cross_banks<3>(x);
+    dpp_cross_banks<2>(x);
+    dpp_cross<kDppSwap2, false>(x, kLow2);
+    dpp_cross<kDppSwap1, false>(x, kLow1);
+    inlane_bitonic(x);
+}
+
+// And the last, of the 512-item runs of the two halves of a wave into one run of 1024 items.
+__device__ __forceinline__ void dpp_merge_1024(uint32_t (&x)[16]) {
+    cross_rows<1>(x);
+    cross_rows<2>(x);
     dpp_cross_banks<3>(x);
     dpp_cross_banks<2>(x);
     dpp_cross<kDppSwap2, false>(x, kLow2);
@@ -536,8 +560,8 @@ __device__ __forceinline__ void serial_merge(const T *lds, uint32_t ai, uint32_t
 // length (runs of E * 2^lv items); when P / E is not a power of two the last run of a pass is
 // shorter (or has no partner).  32-bit elements with E = 16 and P a multiple of 128 merge
 // their first three passes in registers across lanes (dpp_merge_128), the fourth too when P
-// is a multiple of 256 (dpp_merge_256) and the fifth when it is one of 512 (dpp_merge_512).
-// R0 > E: lds already
+// is a multiple of 256 (dpp_merge_256), the fifth when it is one of 512 (dpp_merge_512) and
+// the sixth, across whole waves, when it is one of 1024 (dpp_merge_1024).  R0 > E: lds already
 // holds sorted runs of R0 items (R0 a power of two times E), so sorting starts with the
 // merge pass of those runs.
 // All threads of the block must call it.  COMP: see MergeLess (the register network always
@@ -550,6 +574,7 @@ __device__ __forceinline__ void block_sort(T *lds, uint32_t P, uint32_t R0 = E) 
     const bool dpp = R0 <= E && sizeof(T) == 4 && E == 16 && P % 128 == 0;
     const bool dpp16 = dpp && P % 256 == 0;  // whole 16-lane rows: one more register merge
     const bool dpp32 = dpp && P % 512 == 0;  // whole 32-lane halves: and another
+    const bool dpp64 = dpp && P % 1024 == 0;  // whole waves: and one more
     T x[E];
     if (R0 <= E && act) {
 #pragma unroll
@@ -559,11 +584,17 @@ __device__ __forceinline__ void block_sort(T *lds, uint32_t P, uint32_t R0 = E) 
             if (dpp) dpp_merge_128(x);
             if (dpp16) dpp_merge_256(x);
             if (dpp32) dpp_merge_512(x);
+            if (dpp64) dpp_merge_1024(x);
         }
 #pragma unroll
         for (int k = 0; k < E; ++k) lds[pidx<T>(t * E + k)] = x[k];
     }
-    const uint32_t Rs = R0 > E ? R0 : dpp32 ? 32 * E : dpp16 ? 16 * E : dpp ? 8 * E : E;
+    const uint32_t Rs = R0 > E         ? R0
+                        : dpp64   ? 64 * E
+                        : dpp32   ? 32 * E
+                        : dpp16   ? 16 * E
+                        : dpp     ? 8 * E
+                                  : E;
     for (uint32_t R = Rs, pair = 2 * Rs / E, top = pow2_at_least(Rs); R < P;
          R <<= 1, pair <<= 1, top <<= 1) {
         __syncthreads();
