@@ -134,6 +134,29 @@ def test_one_level_intermediates(ds, dist, case):
     check_level1(geo, ws, tr, n)
 
 
+@pytest.mark.parametrize("kind", ["few_values", "descending"])
+@pytest.mark.parametrize("L", [128, 256, 512, 1024, 4096])
+def test_register_merge_levels(ds, L, kind):
+    """Sublist lengths at which the 32-bit tile sort's in-register merges stop at runs of 128,
+    256, 512 and 1024 items (one wave with 8, 16 or 32 active lanes for L = 128, 256, 512;
+    whole waves from 1024), on inputs made of ties and key-max items or sorted the wrong way.
+    The buckets (padded to multiples of 256) take every level count too.  Output and level-1
+    intermediates against the oracle."""
+    n = min(70_001, 70 * L + 17)  # about 70 sublists where smaller ones would not plan
+    if kind == "few_values":
+        table = np.array([0, 1, 0x7FFFFFFF, 0xFFFFFFFE, 0xFFFFFFFF], dtype=np.uint32)
+        keys = table[synth.draws32(77, n) % np.uint32(table.size)]
+    else:
+        keys = np.sort(synth.uniform_u32(n, 78))[::-1].copy()
+    s = min(64, L // 8)
+    say(f"register merge levels L={L} s={s} {kind}")
+    out, _, geo, ws = gpu_sort(ds, keys, tuning=ds.Tuning(L, s, 0, 0, 1))
+    assert geo.levels == 1 and geo.sublist_len == L
+    ok, _, tr = oracle.dss(keys, L, s, trace=True)
+    assert (out == ok).all()
+    check_level1(geo, ws, tr, n)
+
+
 def test_pairs_u32_stable_intermediates(ds):
     n = 300_001
     say(f"pairs u32 n={n}")
