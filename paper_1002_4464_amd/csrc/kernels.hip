@@ -1300,6 +1300,7 @@ __global__ __launch_bounds__(1024) void k_scan_mid(uint32_t *partial, uint32_t n
     const uint32_t per = (nrb + ng - 1) / ng;
     const uint32_t b0 = min(nrb, grp * per), b1 = min(nrb, b0 + per);
     uint32_t own = 0;
+#pragma unroll 8
     for (uint32_t b = b0; b < b1; ++b) own += partial[(size_t)b * s + j];
     tmp[grp * s + j] = own;
     __syncthreads();
@@ -1309,6 +1310,7 @@ __global__ __launch_bounds__(1024) void k_scan_mid(uint32_t *partial, uint32_t n
         colsum[j] = run + own;
         colbase[j] = run + own;
     }
+#pragma unroll 8
     for (uint32_t b = b0; b < b1; ++b) {
         const uint32_t x = partial[(size_t)b * s + j];
         partial[(size_t)b * s + j] = run;

@@ -29,7 +29,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Largest bucket Step 8 can produce with m sublists of L items and s samples per sublist.
 uint64_t bucket_bound(uint64_t m, uint64_t L, uint64_t s) { return 2 * m * L / s - m; }
 
-constexpr uint32_t kScanRowBlock = 64;
+constexpr uint32_t kScanRowBlock = 32;
 constexpr uint64_t kMaxSamples = 1024;  // per-sublist tables live in LDS
 constexpr uint64_t kMaxPieces = 256;    // pieces per bucket the fused Steps 8-9 accept
 constexpr uint64_t kNumClasses = 8;     // size classes of the fused Steps 8-9
