@@ -1262,6 +1262,7 @@ __global__ __launch_bounds__(256) void k_scan_seg(const uint32_t *counts, uint32
     const uint32_t seg_begin = sv.seg[g].x, seg_size = sv.seg[g].y;
     for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) {
         uint32_t sum = 0;
+#pragma unroll 8
         for (uint32_t i = 0; i < m; ++i) sum += counts[(size_t)(tile0 + i) * s + j];
         colsum[j] = sum;
         colbase[j] = sum;
@@ -1282,6 +1283,7 @@ __global__ __launch_bounds__(256) void k_scan_partial(const uint32_t *counts, ui
     const uint32_t i0 = blockIdx.x * RB, i1 = min(m, i0 + RB);
     for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) {
         uint32_t sum = 0;
+#pragma unroll 8
         for (uint32_t i = i0; i < i1; ++i) sum += counts[(size_t)i * s + j];
         partial[(size_t)blockIdx.x * s + j] = sum;
     }
