@@ -1020,9 +1020,12 @@ __device__ __forceinline__ void rank_chunks(const K *keys, const typename Tr<K, 
     for (uint32_t j0 = wv * kRankBatch; j0 < s; j0 += nwv * kRankBatch) {
         K v[kRankBatch][NQ];
         uint32_t cc[kRankBatch];  // wave-uniform chunk of each global sample of the batch
+        SC gg[kRankBatch];        // and the global samples, loaded together with the chunks
 #pragma unroll
-        for (uint32_t u = 0; u < kRankBatch; ++u)
+        for (uint32_t u = 0; u < kRankBatch; ++u) {
             cc[u] = j0 + u < s ? __builtin_amdgcn_readfirstlane(chunk[j0 + u]) : s;
+            gg[u] = cc[u] < s ? S[(size_t)(j0 + u + 1) * m - 1] : SC{};
+        }
 #pragma unroll
         for (uint32_t u = 0; u < kRankBatch; ++u) {
             const uint32_t c = cc[u];
@@ -1036,7 +1039,7 @@ __device__ __forceinline__ void rank_chunks(const K *keys, const typename Tr<K, 
         for (uint32_t u = 0; u < kRankBatch; ++u) {
             const uint32_t j = j0 + u, c = cc[u];
             if (c >= s) continue;
-            const SC g = S[(size_t)(j + 1) * m - 1];
+            const SC g = gg[u];
             uint32_t le = 0;
 #pragma unroll
             for (uint32_t q = 0; q < NQ; ++q) {
