@@ -62,7 +62,7 @@ STAGE_GROUPS = {
 
 
 def group_bytes(group: str, n: int, g, kb: int) -> float:
-    """Algorithmic HBM bytes one step of a stage group must move (the design doc lists them):
+    """Algorithmic HBM bytes one step of a stage group must move:
     a sort or move of the data reads and writes n keys once; ranking reads the sorted sublists
     once plus the splitters and writes the counts; samples, counts and offsets are small."""
     sb = g.sample_bytes
