@@ -152,7 +152,9 @@ int dsort_plan_geometry(dsort_plan_t plan, uint64_t n, dsort_geometry_t *out);
  * sorts may also run on side streams (three per device, created by the library on the first
  * call made outside stream capture and kept for the process); the call ends by enqueueing on
  * `stream` a wait for them, so work enqueued on `stream` afterwards sees the sorted result.
- * Calls from several host threads are safe; their bucket sorts then share the side streams.
+ * A call made while `stream` is being captured into a graph runs everything on `stream` (the
+ * side streams never enter a capture).  Calls from several host threads are safe; their
+ * bucket sorts then share the side streams.
  * Errors: DSORT_E_INVALID (bad plan or pointer, misalignment, values given to a keys-only plan
  * or missing for a pairs plan, n or num_segments above the plan's), DSORT_E_UNSUPPORTED
  * (max_segment above segment_limit), DSORT_E_HIP.  n = 0 or num_segments = 0 is a no-op. */

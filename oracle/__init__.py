@@ -55,6 +55,12 @@ def _load():
         lib.oracle_dss.argtypes = [ctypes.c_int, P, P, ctypes.c_uint64, ctypes.c_uint64,
                                    ctypes.c_uint64, P, P, ctypes.POINTER(_Trace)]
         lib.oracle_dss.restype = ctypes.c_int
+        lib.oracle_dss_sampled.argtypes = [ctypes.c_int, P, P, ctypes.c_uint64, ctypes.c_uint64,
+                                           ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64, P, P,
+                                           ctypes.POINTER(_Trace)]
+        lib.oracle_dss_sampled.restype = ctypes.c_int
+        lib.oracle_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        lib.oracle_splitmix64.restype = ctypes.c_uint64
         lib.oracle_stable_sort.argtypes = [ctypes.c_int, P, P, ctypes.c_uint64, P, P]
         lib.oracle_stable_sort.restype = ctypes.c_int
         lib.oracle_f32_order.argtypes = [ctypes.c_uint32]
@@ -95,10 +101,13 @@ class Trace:
 
 
 def dss(keys: np.ndarray, L: int, s: int, values: np.ndarray | None = None,
-        trace: bool = False):
+        trace: bool = False, reloc: bool = True, sampling: int = 0, seed: int = 0):
     """Algorithm 1 on ``keys`` (uint32, uint64 or float32) with sublist length L, s samples.
 
-    Returns ``(sorted_keys, sorted_values_or_None, Trace_or_None)``.
+    Returns ``(sorted_keys, sorted_values_or_None, Trace_or_None)``.  With ``reloc=False`` the
+    trace leaves out the array after Step 8 (``reloc_key``/``reloc_val`` are None), which at
+    large n is the bulk of its memory.  ``sampling=1`` takes Step 3's samples at random
+    positions drawn from ``seed`` (the randomized-splitter variant, reading R8 of the C source).
     """
     lib = _load()
     keys = np.ascontiguousarray(keys)
@@ -117,11 +126,14 @@ def dss(keys: np.ndarray, L: int, s: int, values: np.ndarray | None = None,
         tr_obj = Trace(n, L, s, m,
                        np.empty(m * s, u64), np.empty(m * s, u64), np.empty(s, u64),
                        np.empty(s, u64), np.empty((m, s), u64), np.empty((m, s), u64),
-                       np.empty(s, u64), np.empty(m * L, keys.dtype), np.empty(m * L, np.uint32))
+                       np.empty(s, u64), np.empty(m * L, keys.dtype) if reloc else None,
+                       np.empty(m * L, np.uint32) if reloc else None)
         tr_ptr = ctypes.pointer(_Trace(*[_ptr(getattr(tr_obj, f)) for f, _ in _Trace._fields_]))
-    rc = lib.oracle_dss(kind, _ptr(keys), _ptr(values), n, L, s, _ptr(out_k), _ptr(out_v), tr_ptr)
+    rc = lib.oracle_dss_sampled(kind, _ptr(keys), _ptr(values), n, L, s, int(sampling),
+                                int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(out_k), _ptr(out_v), tr_ptr)
     if rc != 0:
-        raise ValueError(f"oracle_dss failed with status {rc} (n={n}, L={L}, s={s})")
+        raise ValueError(f"oracle_dss failed with status {rc} (n={n}, L={L}, s={s}, "
+                         f"sampling={sampling})")
     return out_k, out_v, tr_obj
 
 
@@ -159,6 +171,11 @@ def segmented_sort(keys: np.ndarray, offsets, values: np.ndarray | None = None):
         if values is not None:
             out_v[lo:hi] = v
     return out_k, out_v
+
+
+def splitmix64(seed: int, c: int) -> int:
+    """Draw ``c`` of the oracle's own SplitMix64 stream seeded with ``seed`` (reading R8)."""
+    return int(_load().oracle_splitmix64(int(seed) & 0xFFFFFFFFFFFFFFFF, int(c)))
 
 
 def f32_order(bits: int) -> int:

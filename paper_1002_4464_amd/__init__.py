@@ -239,7 +239,7 @@ class Plan:
         _check(rc, "dsort_plan")
         self._h = h
         self.workspace_bytes = int(ws.value)
-        self._ws = None
+        self._ws = {}
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -290,7 +290,7 @@ class Plan:
             vp = ctypes.c_void_p(self._dev_ptr(values, 4, "values"))
             sv = torch.empty_like(values)
             svp = ctypes.c_void_p(sv.data_ptr())
-        ws = workspace if workspace is not None else self.workspace(keys.device)
+        ws = workspace if workspace is not None else self.workspace(keys.device, stream)
         t = SegTuning()
         rc = self._lib.dsort_autotune_segmented(
             self._h, ctypes.c_void_p(kp), vp, keys.numel(), ctypes.c_void_p(op),
@@ -317,13 +317,25 @@ class Plan:
                "dsort_stage_times")
         return {names[i].decode(): (float(ms[i]), int(cnt[i])) for i in range(min(c.value, cap))}
 
-    def workspace(self, device):
-        """A workspace tensor (uint8, plan.workspace_bytes) on ``device``, cached."""
+    def workspace(self, device, stream=None):
+        """A workspace tensor (uint8, plan.workspace_bytes) on ``device`` for calls enqueued on
+        ``stream`` (default: the device's current stream), cached per (device, stream).  A
+        workspace holds a call's intermediates until the call's kernels finish, so one
+        workspace must never serve two streams at once; calls that pass no workspace get the
+        one of their own stream."""
         import torch
-        if self._ws is None or self._ws.device != torch.device(device):
-            self._ws = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8,
-                                   device=device)
-        return self._ws
+        dev = torch.device(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        key = (str(dev), int(stream.cuda_stream))
+        ws = self._ws.get(key)
+        if ws is None:
+            # allocated on the stream that will use it (the caching allocator ties blocks to
+            # their allocation stream)
+            with torch.cuda.stream(stream):
+                ws = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=dev)
+            self._ws[key] = ws
+        return ws
 
     @staticmethod
     def _dev_ptr(t, itemsize: int, what: str) -> int:
@@ -347,7 +359,7 @@ class Plan:
             raise ValueError("plan was made for key/value sorts")
         ksz = 8 if self.key_type == U64 else 4
         kp = self._dev_ptr(keys, ksz, "keys")
-        ws = workspace if workspace is not None else self.workspace(keys.device)
+        ws = workspace if workspace is not None else self.workspace(keys.device, stream)
         rc = self._lib.dsort_keys(self._h, ctypes.c_void_p(kp), keys.numel(),
                                   ctypes.c_void_p(ws.data_ptr()), self._stream(stream, keys.device))
         _check(rc, "dsort_keys")
@@ -362,7 +374,7 @@ class Plan:
         ksz = 8 if self.key_type == U64 else 4
         kp = self._dev_ptr(keys, ksz, "keys")
         vp = self._dev_ptr(values, 4, "values")
-        ws = workspace if workspace is not None else self.workspace(keys.device)
+        ws = workspace if workspace is not None else self.workspace(keys.device, stream)
         rc = self._lib.dsort_pairs(self._h, ctypes.c_void_p(kp), ctypes.c_void_p(vp),
                                    keys.numel(), ctypes.c_void_p(ws.data_ptr()),
                                    self._stream(stream, keys.device))
@@ -386,7 +398,7 @@ class Plan:
             if values.numel() != keys.numel():
                 raise ValueError("keys and values differ in length")
             vp = ctypes.c_void_p(self._dev_ptr(values, 4, "values"))
-        ws = workspace if workspace is not None else self.workspace(keys.device)
+        ws = workspace if workspace is not None else self.workspace(keys.device, stream)
         rc = self._lib.dsort_segmented(self._h, ctypes.c_void_p(kp), vp, keys.numel(),
                                        ctypes.c_void_p(op), offsets.numel() - 1, int(max_segment),
                                        ctypes.c_void_p(ws.data_ptr()),
@@ -421,7 +433,9 @@ def _plan_for(key_type: int, values: bool, n: int) -> Plan:
 
 def sort(keys, key_type: int | None = None, stream=None):
     """Sorts a contiguous device tensor in place (4-byte elements: uint32 order, or float32
-    totalOrder for float32 tensors; 8-byte elements: uint64 order) and returns it."""
+    totalOrder for float32 tensors; 8-byte elements: uint64 order) and returns it.  The work is
+    enqueued on ``stream`` (default: the current stream) with a workspace kept for that stream,
+    so calls on different streams never share intermediates."""
     kt = _key_type_of(keys, key_type)
     return _plan_for(kt, False, keys.numel()).sort_keys(keys, stream=stream)
 

@@ -1357,34 +1357,18 @@ struct GatherArgs {
 
 constexpr uint32_t kMaxPieces = 256;
 
-// Items per thread of the merge-sort bucket kernel: 16 (8 for 16-byte elements), raised so that
-// CAP / E <= 1024 threads.
-#ifndef DSORT_PAIR_GATHER_E
-#define DSORT_PAIR_GATHER_E 8  // items per thread of the key/value bucket sorts
-#endif
-#ifndef DSORT_PAIR_GATHER_WPE
-#define DSORT_PAIR_GATHER_WPE 4  // minimum waves per SIMD asked of the key/value bucket sorts
-#endif
-#ifndef DSORT_KEY_GATHER_E_6144
-#define DSORT_KEY_GATHER_E_6144 16
-#endif
-#ifndef DSORT_KEY_GATHER_E_10240
-#define DSORT_KEY_GATHER_E_10240 20
-#endif
-#ifndef DSORT_KEY_GATHER_E_12288
-#define DSORT_KEY_GATHER_E_12288 16
-#endif
+// Items per thread of the merge-sort bucket kernels: 16 (8 for 16-byte elements and for
+// key/value sorts, whose kernels also ask for at least four waves per SIMD), 20 for the 10K
+// class of 32-bit keys (its buckets then take as many merge passes as the 8K class), raised so
+// that CAP / E <= 1024 threads.
 template <class K, bool V, int CAP> struct GatherE {
     static constexpr bool keys32 = !V && sizeof(K) == 4;
-    static constexpr int base =
-        sizeof(typename Tr<K, V>::T) >= 16 ? 8
-        : V                                 ? DSORT_PAIR_GATHER_E
-        : keys32 && CAP == 6144             ? DSORT_KEY_GATHER_E_6144
-        : keys32 && CAP == 10240            ? DSORT_KEY_GATHER_E_10240
-        : keys32 && CAP == 12288            ? DSORT_KEY_GATHER_E_12288
-                                            : 16;
+    static constexpr int base = sizeof(typename Tr<K, V>::T) >= 16 ? 8
+                                : V                                 ? 8
+                                : keys32 && CAP == 10240            ? 20
+                                                                    : 16;
     static constexpr int E = CAP / base > 1024 ? (CAP / 1024 <= 16 ? 16 : 32) : base;
-    static constexpr int wpe = V ? DSORT_PAIR_GATHER_WPE : 1;
+    static constexpr int wpe = V ? 4 : 1;
     static_assert(CAP % E == 0 && CAP / E <= 1024 && (CAP / E) % 64 == 0, "bucket class shape");
 };
 
@@ -1688,9 +1672,6 @@ constexpr uint32_t kNumCUs = 256;
 // device for the process (default priority, non-blocking), created on the first call that is
 // not being captured; a call's fork and join are enqueued under one lock, so that calls from
 // several host threads never interleave their event records.
-#ifndef DSORT_FORK_CLASSES
-#define DSORT_FORK_CLASSES 1  // 0: every class on the call's stream
-#endif
 constexpr int kForkStreams = 3;
 struct ForkSet {
     hipStream_t side[kForkStreams];
@@ -1801,7 +1782,14 @@ template <class K, bool V, bool F32> struct Pipeline {
         hipStream_t cs[kMaxClasses];
         for (auto &c : cs) c = st;
         if (forked) *forked = false;
-        if (!DSORT_FORK_CLASSES || !fork || tm) return gather_classes<0, XIN>(a, cs, tm);
+        if (!fork || tm) return gather_classes<0, XIN>(a, cs, tm);
+        // A call being captured into a graph stays on its own stream: forking would pull the
+        // shared side streams into the capture, where other threads' calls enqueue too.
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) {
+            (void)hipGetLastError();
+            return gather_classes<0, XIN>(a, cs, tm);
+        }
         int rc;
         {
             std::lock_guard<std::mutex> lock(g_fork_mu);

@@ -1,7 +1,8 @@
 // Served sort stream: the device side of the scheduler in server_core.h and its C ABI.
 //
 // A server owns one device arena of the HBM budget, `lanes` HIP streams of default priority with
-// one completion event each, and per lane a pinned host table for batch descriptors.  A launch
+// one completion event each, and per lane pinned host memory for batch descriptors and for the
+// unit's kernel status word (read back with the unit; a non-zero word fails its requests).  A launch
 // is admitted when its requests' data plus its workspace fit what is left of the budget; the
 // workspace part is carved from the arena (the data part is reserved there too, unused, so one
 // allocator keeps the account).  A plain
@@ -10,6 +11,7 @@
 // block, runs one segmented sort over them (each request one segment), and copies the results
 // back, all on its lane's stream.
 #include <hip/hip_runtime_api.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <new>
@@ -45,7 +47,8 @@ class HipExecutor : public srv::Executor {
             streams_.push_back(s);
             if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return DSORT_E_HIP;
             events_.push_back(e);
-            if (hipHostMalloc(&h, table_bytes_, hipHostMallocDefault) != hipSuccess)
+            // the batch descriptor table, then one word for the unit's kernel status flags
+            if (hipHostMalloc(&h, table_bytes_ + 256, hipHostMallocDefault) != hipSuccess)
                 return DSORT_E_HIP;
             pinned_.push_back(h);
         }
@@ -99,76 +102,110 @@ class HipExecutor : public srv::Executor {
         const size_t lane = (size_t)u.lane;
         hipStream_t st = streams_[lane];
         char *blk = (char *)arena_ + u.ws_off;
-        int rc = DSORT_OK;
-        if (!u.batched) {
-            srv::Request *r = u.reqs[0];
-            if (r->n > 1) {
-                Geom g;
-                rc = make_geom(r->key_type, r->values, r->n, dsort_tuning_t{}, g);
-                if (rc == DSORT_OK) rc = run_pipeline(g, r->keys, r->vals, blk, st, nullptr);
-            }
-        } else {
-            const uint32_t S = (uint32_t)u.reqs.size();
-            SegGeom sg;
-            rc = make_seg_geom(u.key_type, u.values, u.total, S, u.max_seg, SegTuning{}, sg);
-            if (rc != DSORT_OK) return rc;
-            char *p = blk + al256(sg.total);
-            void *stage_keys = p;
-            p += al256(u.total * key_bytes_of(u.key_type));
-            uint32_t *stage_vals = nullptr;
-            if (u.values) {
-                stage_vals = (uint32_t *)p;
-                p += al256(u.total * 4);
-            }
-            char *dev_tab = p;
-            // descriptor table: S key pointers, S value pointers, S + 1 offsets
-            uint64_t *h = (uint64_t *)pinned_[lane];
-            uint64_t pos = 0;
-            for (uint32_t i = 0; i < S; ++i) {
-                const srv::Request *r = u.reqs[i];
-                h[i] = (uint64_t)(uintptr_t)r->keys;
-                h[S + i] = (uint64_t)(uintptr_t)r->vals;
-                h[2 * S + i] = pos;
-                pos += r->n;
-            }
-            h[3 * S] = pos;
-            const size_t tb = ((size_t)3 * S + 1) * 8;
-            if (hipMemcpyAsync(dev_tab, h, tb, hipMemcpyHostToDevice, st) != hipSuccess) {
-                set_last_error("batch table", "hipMemcpyAsync", "failed");
-                (void)hipGetLastError();
-                return DSORT_E_HIP;
-            }
-            const uint64_t *d_keysp = (const uint64_t *)dev_tab;
-            const uint64_t *d_valsp = d_keysp + S;
-            const uint64_t *d_off = d_keysp + 2 * S;
-            const int kb = (int)key_bytes_of(u.key_type);
-            rc = launch_pack(kb, d_keysp, d_valsp, d_off, S, u.total, stage_keys, stage_vals,
-                             false, st);
-            if (rc == DSORT_OK)
-                rc = run_segmented(sg, stage_keys, stage_vals, d_off, blk, st, nullptr);
-            if (rc == DSORT_OK)
-                rc = launch_pack(kb, d_keysp, d_valsp, d_off, S, u.total, stage_keys,
-                                 stage_vals, true, st);
-        }
-        if (rc != DSORT_OK) return rc;
-        if (hipEventRecord(events_[lane], st) != hipSuccess) {
+        // The lane's previous unit has finished (its lane was free), so its status word is
+        // no longer being written.
+        uint32_t *status = lane_status(lane);
+        *status = 0;
+        const int rc = enqueue(u, st, blk);
+        // The unit's status flags (the first word of its workspace block) come back with the
+        // unit; poll() fails the unit if a kernel raised any.
+        if (rc == DSORT_OK && ran_pipeline(u) &&
+            hipMemcpyAsync(status, blk, 4, hipMemcpyDeviceToHost, st) != hipSuccess) {
             (void)hipGetLastError();
+            (void)hipStreamSynchronize(st);
             return DSORT_E_HIP;
         }
-        return DSORT_OK;
+        // Recorded after a failure too: whatever was enqueued before it must have finished
+        // before poll() lets the scheduler hand the block and the lane to another unit.
+        if (hipEventRecord(events_[lane], st) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipStreamSynchronize(st);
+            (void)hipEventSynchronize(events_[lane]);
+            return rc != DSORT_OK ? rc : DSORT_E_HIP;
+        }
+        return rc;
     }
 
     int poll(srv::Unit &u) override {
         const hipError_t e = hipEventQuery(events_[(size_t)u.lane]);
-        if (e == hipSuccess) return 1;
         if (e == hipErrorNotReady) return 0;
-        set_last_error("server", hipGetErrorName(e), hipGetErrorString(e));
-        return DSORT_E_HIP;
+        if (e != hipSuccess) {
+            set_last_error("server", hipGetErrorName(e), hipGetErrorString(e));
+            return DSORT_E_HIP;
+        }
+        const uint32_t flags = *lane_status((size_t)u.lane);
+        if (flags != 0) {
+            char buf[64];
+            snprintf(buf, sizeof buf, "kernel status flags 0x%x", flags);
+            set_last_error("server", "unit failed", buf);
+            return DSORT_E_HIP;
+        }
+        return 1;
     }
 
     void on_thread_start() override { (void)hipSetDevice(device_); }
 
   private:
+    uint32_t *lane_status(size_t lane) const {
+        return (uint32_t *)((char *)pinned_[lane] + table_bytes_);
+    }
+
+    static bool ran_pipeline(const srv::Unit &u) { return u.batched || u.reqs[0]->n > 1; }
+
+    // Enqueues the unit's work on st; returns the first failure (work enqueued before it stays
+    // enqueued).
+    int enqueue(srv::Unit &u, hipStream_t st, char *blk) {
+        const size_t lane = (size_t)u.lane;
+        if (!u.batched) {
+            srv::Request *r = u.reqs[0];
+            if (r->n <= 1) return DSORT_OK;
+            Geom g;
+            const int rc = make_geom(r->key_type, r->values, r->n, dsort_tuning_t{}, g);
+            return rc == DSORT_OK ? run_pipeline(g, r->keys, r->vals, blk, st, nullptr) : rc;
+        }
+        const uint32_t S = (uint32_t)u.reqs.size();
+        SegGeom sg;
+        int rc = make_seg_geom(u.key_type, u.values, u.total, S, u.max_seg, SegTuning{}, sg);
+        if (rc != DSORT_OK) return rc;
+        char *p = blk + al256(sg.total);
+        void *stage_keys = p;
+        p += al256(u.total * key_bytes_of(u.key_type));
+        uint32_t *stage_vals = nullptr;
+        if (u.values) {
+            stage_vals = (uint32_t *)p;
+            p += al256(u.total * 4);
+        }
+        char *dev_tab = p;
+        // descriptor table: S key pointers, S value pointers, S + 1 offsets
+        uint64_t *h = (uint64_t *)pinned_[lane];
+        uint64_t pos = 0;
+        for (uint32_t i = 0; i < S; ++i) {
+            const srv::Request *r = u.reqs[i];
+            h[i] = (uint64_t)(uintptr_t)r->keys;
+            h[S + i] = (uint64_t)(uintptr_t)r->vals;
+            h[2 * S + i] = pos;
+            pos += r->n;
+        }
+        h[3 * S] = pos;
+        const size_t tb = ((size_t)3 * S + 1) * 8;
+        if (hipMemcpyAsync(dev_tab, h, tb, hipMemcpyHostToDevice, st) != hipSuccess) {
+            set_last_error("batch table", "hipMemcpyAsync", "failed");
+            (void)hipGetLastError();
+            return DSORT_E_HIP;
+        }
+        const uint64_t *d_keysp = (const uint64_t *)dev_tab;
+        const uint64_t *d_valsp = d_keysp + S;
+        const uint64_t *d_off = d_keysp + 2 * S;
+        const int kb = (int)key_bytes_of(u.key_type);
+        rc = launch_pack(kb, d_keysp, d_valsp, d_off, S, u.total, stage_keys, stage_vals, false,
+                         st);
+        if (rc == DSORT_OK) rc = run_segmented(sg, stage_keys, stage_vals, d_off, blk, st, nullptr);
+        if (rc == DSORT_OK)
+            rc = launch_pack(kb, d_keysp, d_valsp, d_off, S, u.total, stage_keys, stage_vals,
+                             true, st);
+        return rc;
+    }
+
     int device_ = 0;
     uint32_t max_req_ = 0;
     void *arena_ = nullptr;
@@ -226,14 +263,9 @@ int dsort_server_create(dsort_server_t *out, uint64_t hbm_budget_bytes, uint32_t
 int dsort_submit(dsort_server_t srv, const dsort_request_t *req, uint64_t *ticket) {
     if (!server_ok(srv) || !req || !ticket) return DSORT_E_INVALID;
     const int kt = req->key_type;
-    if (kt != DSORT_U32 && kt != DSORT_U64 && kt != DSORT_F32) return DSORT_E_INVALID;
-    if (req->with_values != 0 && req->with_values != 1) return DSORT_E_INVALID;
-    if (req->n > dsort::kMaxItems) return DSORT_E_INVALID;
-    if (req->n > 1) {
-        if (!req->d_keys || (req->with_values && !req->d_values)) return DSORT_E_INVALID;
-        if (((uintptr_t)req->d_keys & (kt == DSORT_U64 ? 7 : 3)) != 0) return DSORT_E_INVALID;
-        if (req->with_values && ((uintptr_t)req->d_values & 3) != 0) return DSORT_E_INVALID;
-    }
+    if (!dsort::srv::request_valid(kt, req->with_values, req->d_keys, req->d_values, req->n,
+                                   dsort::kMaxItems))
+        return DSORT_E_INVALID;
     dsort::srv::Request r;
     r.key_type = kt;
     r.values = req->with_values != 0;

@@ -105,6 +105,22 @@ class Arena {
 
 enum ReqState { kQueued = 0, kRunning = 1, kDone = 2 };
 
+// Checks one submitted request: a known key type (1 uint32, 2 uint64, 3 float32), values
+// flag 0 or 1, n within `max_items`, and for every n >= 1 key (and value) pointers that are
+// non-null and naturally aligned.  A request of one item is still read and written in place by
+// the batch staging copies, so n = 1 needs valid pointers too; only n = 0 may pass null.
+inline bool request_valid(int key_type, int with_values, const void *keys, const void *vals,
+                          uint64_t n, uint64_t max_items) {
+    if (key_type != 1 && key_type != 2 && key_type != 3) return false;
+    if (with_values != 0 && with_values != 1) return false;
+    if (n > max_items) return false;
+    if (n == 0) return true;
+    if (!keys || (with_values && !vals)) return false;
+    if (((uintptr_t)keys & (key_type == 2 ? 7u : 3u)) != 0) return false;
+    if (with_values && ((uintptr_t)vals & 3u) != 0) return false;
+    return true;
+}
+
 struct Request {
     uint64_t ticket = 0;
     int key_type = 0;
@@ -120,6 +136,7 @@ struct Request {
 struct Unit {
     uint64_t id = 0;
     int lane = -1;
+    int failed = 0;                        // launch status when the launch failed
     int key_type = 0;
     bool values = false;
     bool batched = false;
@@ -139,7 +156,9 @@ class Executor {
     // Arena bytes of one unit (0 = impossible).
     virtual uint64_t unit_bytes(const Unit &u) const = 0;
     // Enqueue the unit on its lane; ws is the arena offset of its block.  Returns 0 or a
-    // negative status (the unit's requests then fail with it).
+    // negative status (the unit's requests then fail with it).  A failed launch may have
+    // enqueued part of the unit's work: poll() must still report the unit finished only once
+    // nothing enqueued for it can touch its block or its requests' buffers any more.
     virtual int launch(Unit &u) = 0;
     // 1 finished, 0 still running, negative: failed with that status.
     virtual int poll(Unit &u) = 0;
@@ -315,7 +334,7 @@ class Scheduler {
                 ++i;
                 continue;
             }
-            finish(u, p);
+            finish(u, u->failed ? u->failed : p);
             delete u;
             running_.erase(running_.begin() + (long)i);
             changed = true;
@@ -380,14 +399,11 @@ class Scheduler {
                 st_.batched_requests += u->reqs.size();
                 st_.max_batch = std::max<uint64_t>(st_.max_batch, u->reqs.size());
             }
-            const int rc = ex_->launch(*u);
-            if (rc != 0) {
-                finish(u, rc);
-                delete u;
-            } else {
-                running_.push_back(u);
-                st_.peak_running = std::max<uint64_t>(st_.peak_running, running_.size());
-            }
+            // A failed launch keeps its block and lane until poll() reports the lane drained:
+            // work enqueued before the failure may still write them.
+            u->failed = ex_->launch(*u);
+            running_.push_back(u);
+            st_.peak_running = std::max<uint64_t>(st_.peak_running, running_.size());
             changed = true;
         }
         return changed;

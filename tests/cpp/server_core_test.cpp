@@ -41,11 +41,16 @@ struct FakeExec : Executor {
         return u.batched ? 1024 + u.total * 8 + u.reqs.size() * 16 : 512 + u.total * 4;
     }
     int launch(Unit &u) override {
-        if ((int)u.id == fail_launch_on) return -4;
+        if (polls.size() <= u.id) polls.resize(u.id + 1, 0);
+        if ((int)u.id == fail_launch_on) {
+            // part of the unit's work was enqueued before the failure: it still occupies the
+            // lane until poll() reports it drained
+            ++running;
+            return -4;
+        }
         std::vector<uint64_t> t;
         for (auto *r : u.reqs) t.push_back(r->ticket);
         launched.push_back(t);
-        if (polls.size() <= u.id) polls.resize(u.id + 1, 0);
         int now = ++running;
         if (now > max_running) max_running = now;
         return 0;
@@ -219,6 +224,51 @@ static void test_inflight_cap() {
     printf("OK inflight_cap\n");
 }
 
+// A failed launch keeps its arena block and lane until the executor reports the lane drained.
+static void test_failed_launch_holds_block() {
+    FakeExec ex;
+    ex.nl = 1;
+    ex.fail_launch_on = 1;
+    Scheduler s(&ex, 1 << 20, 64);
+    uint64_t a, b;
+    CHECK(s.submit(req(5000), &a, nullptr) == 0);
+    CHECK(s.submit(req(6000), &b, nullptr) == 0);
+    s.step();
+    CHECK(s.arena_used() > 0);       // unit 1 failed to launch but its block is still held
+    CHECK(state(s, a) == kRunning);  // and its request is not reported yet
+    CHECK(ex.launched.empty());      // the only lane is still taken: unit 2 waits
+    s.step();
+    CHECK(ex.launched.empty() && state(s, b) == kQueued);
+    ex.finished.insert(1);           // the lane drains
+    s.step();
+    CHECK(state(s, a) == -4);
+    CHECK(ex.launched.size() == 1 && state(s, b) == kRunning);
+    ex.finished.insert(2);
+    s.drain();
+    CHECK(state(s, b) == kDone && s.arena_used() == 0);
+    printf("OK failed_launch_holds_block\n");
+}
+
+// Submitted requests: every n >= 1 needs valid, aligned pointers (batch staging reads and writes
+// even one-item requests); only n = 0 may pass null.
+static void test_request_validation() {
+    alignas(16) static uint64_t buf[4];
+    char *p = (char *)buf;
+    const uint64_t mx = 1ull << 32;
+    CHECK(request_valid(1, 0, p, nullptr, 1, mx));
+    CHECK(!request_valid(1, 0, nullptr, nullptr, 1, mx));
+    CHECK(!request_valid(1, 1, p, nullptr, 1, mx));
+    CHECK(!request_valid(2, 0, p + 4, nullptr, 1, mx));
+    CHECK(!request_valid(1, 0, p + 2, nullptr, 5, mx));
+    CHECK(!request_valid(1, 1, p, p + 1, 1, mx));
+    CHECK(request_valid(2, 1, p, p + 4, 2, mx));
+    CHECK(request_valid(3, 0, nullptr, nullptr, 0, mx));
+    CHECK(!request_valid(4, 0, p, nullptr, 1, mx));
+    CHECK(!request_valid(1, 2, p, p, 1, mx));
+    CHECK(!request_valid(1, 0, p, nullptr, mx + 1, mx));
+    printf("OK request_validation\n");
+}
+
 static void test_failures() {
     FakeExec ex;
     ex.fail_launch_on = 1;
@@ -288,6 +338,8 @@ int main() {
     test_batch_halves_to_fit();
     test_inflight_cap();
     test_failures();
+    test_failed_launch_holds_block();
+    test_request_validation();
     test_threaded_stream();
     printf("ALL OK\n");
     return 0;

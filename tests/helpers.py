@@ -1,7 +1,51 @@
-"""Shared test helpers: moving numpy arrays to and from the GPU, and reading the workspace."""
+"""Shared test helpers: moving numpy arrays to and from the GPU, reading the workspace, and
+running independent oracle calls on several host threads (the oracle is single-threaded C
+called through ctypes, which releases the GIL, so independent calls run side by side)."""
+import os
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
+
+# Host threads for oracle work (a GPU machine gives one GPU 16 host cores).
+ORACLE_THREADS = max(1, min(16, os.cpu_count() or 1))
+_pool = None
+
+
+def oracle_pool() -> ThreadPoolExecutor:
+    """Process-wide thread pool for oracle calls that run beside GPU work."""
+    global _pool
+    if _pool is None:
+        _pool = ThreadPoolExecutor(max_workers=ORACLE_THREADS)
+    return _pool
+
+
+def oracle_segmented(keys: np.ndarray, offsets, values=None, threads: int = ORACLE_THREADS):
+    """``oracle.segmented_sort`` computed with segments spread over ``threads`` host threads
+    (each thread runs the oracle's stable sort on its own segments, in place of one loop)."""
+    import oracle
+    offsets = [int(x) for x in offsets]
+    out_k = np.array(keys, copy=True)
+    out_v = np.array(values, dtype=np.uint32, copy=True) if values is not None else None
+    segs = [(lo, hi) for lo, hi in zip(offsets[:-1], offsets[1:]) if hi - lo >= 2]
+    for lo, hi in segs:
+        if not 0 <= lo <= hi <= keys.size:
+            raise ValueError(f"bad segment [{lo}, {hi})")
+
+    def run(part):
+        for lo, hi in part:
+            k, v = oracle.stable_sort(keys[lo:hi], None if values is None else values[lo:hi])
+            out_k[lo:hi] = k
+            if values is not None:
+                out_v[lo:hi] = v
+
+    # deal segments round-robin by size so every thread gets a similar share
+    order = sorted(segs, key=lambda r: r[0] - r[1])
+    parts = [order[i::threads] for i in range(threads)]
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        for f in [ex.submit(run, part) for part in parts if part]:
+            f.result()
+    return out_k, out_v
 
 _VIEW = {np.dtype(np.uint32): np.int32, np.dtype(np.float32): np.int32,
          np.dtype(np.uint64): np.int64}

@@ -1,15 +1,17 @@
 """GPU parity: the HIP pipeline (called through the C ABI) against the CPU oracle.
 
 Integer work, so the bar is bit-exact everywhere: final outputs, and the level-1 intermediates
-of Algorithm 1 (sorted samples, global samples, a_ij, l_ij, bucket table) at the same (L, s).
-At full benchmark sizes the output is checked against numpy's sort (the plain definition) and,
-for key/value sorts, by properties that fix the stable result uniquely."""
+of Algorithm 1 (sorted samples, global samples, a_ij, l_ij, bucket table) at the same (L, s),
+on every configuration up to the full benchmark sizes (2^28 uint32 keys with the benchmark's own
+plan, the six 2^26 distributions, 2^27 uint64 key/value pairs).  The oracle runs for the large
+inputs are started on host threads when the module's first test runs, so they overlap the GPU
+tests before them."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from helpers import from_dev, samples_from_ws, say, to_dev, ws_view
+from helpers import from_dev, oracle_pool, samples_from_ws, say, to_dev, ws_view
 
 pytestmark = pytest.mark.gpu
 
@@ -17,12 +19,61 @@ KT = {np.dtype(np.uint32): 1, np.dtype(np.uint64): 2, np.dtype(np.float32): 3}
 
 
 @pytest.fixture(scope="module")
-def ds():
+def ds(request):
     import torch
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     import paper_1002_4464_amd as d
     d.load_library()
+    _start_heavy(d, {it.name for it in request.session.items})
     return d
+
+
+C2_SEEDS = {"uniform": 2, "gaussian": 3, "bucket": 4, "staggered": 5, "sorted": 6, "equal": 7}
+_HEAVY = {}
+
+
+def _auto_plan(d, kt, values, n):
+    g = d.Plan(kt, values, n).geometry(n)
+    return g.sublist_len, g.samples
+
+
+def _start_heavy(d, selected):
+    """Submits the oracle runs of the large configurations whose tests are selected (each run
+    generates its own copy of the seeded input, so the tests generate theirs for the GPU
+    meanwhile)."""
+    if _HEAVY:
+        return
+    pool = oracle_pool()
+
+    def job(key, test, make, L, s, values=False):
+        if test not in selected:
+            return
+
+        def run():
+            keys = make()
+            vals = synth.index_values(keys.size) if values else None
+            return oracle.dss(keys, L, s, values=vals, trace=True, reloc=False)
+        _HEAVY[key] = pool.submit(run)
+
+    n28, n27, n26 = 1 << 28, 1 << 27, 1 << 26
+    # the benchmark's plan: L = 16384, s = 256, 2^22 samples sorted in 8 merge rounds
+    job("2p28", "test_headline_2p28_uniform", lambda: synth.uniform_u32(n28, 8), 16384, 256)
+    L26, s26 = _auto_plan(d, 1, False, n26)
+    for dist, seed in C2_SEEDS.items():
+        job("2p26_" + dist, f"test_2p26_distributions[{dist}]",
+            lambda dist=dist, seed=seed: synth.make_u32(dist, n26, seed), L26, s26)
+    L27, s27 = _auto_plan(d, 2, True, n27)
+    job("c3b_uniform", "test_2p27_u64_pairs[uniform]", lambda: synth.uniform_u64(n27, 9),
+        L27, s27, values=True)
+    job("c3b_zipf", "test_2p27_u64_pairs[zipf]", lambda: synth.zipf_u64(n27, 10), L27, s27,
+        values=True)
+    Lu, su = _auto_plan(d, 2, False, n26)
+    job("u64_2p26", "test_two_level_u64_keys_2p26", lambda: synth.zipf_u64(n26, 17), Lu, su)
+
+
+def _heavy(key):
+    """The oracle result of one large configuration (released once taken)."""
+    return _HEAVY.pop(key).result()
 
 
 def gpu_sort(ds, keys, values=None, tuning=None, plan=None):
@@ -259,60 +310,98 @@ def test_two_level_auto_2p24(ds):
     check_level1(geo, ws, tr, n)
 
 
+def test_module_sort_on_two_streams(ds):
+    """The module-level ds.sort() keeps one plan per size class; two calls of one class enqueued
+    on two streams at once each get their own stream's workspace, so both results match the
+    oracle."""
+    import torch
+    n = 3_000_001
+    inputs = [synth.uniform_u32(n, 91), synth.make_u32("bucket", n, 92)]
+    wants = [oracle.stable_sort(k)[0] for k in inputs]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for rep in range(3):
+        say(f"two streams, round {rep}")
+        devs = [to_dev(k) for k in inputs]
+        torch.cuda.synchronize()
+        for t, st in zip(devs, streams):
+            ds.sort(t, stream=st)
+        torch.cuda.synchronize()
+        for t, w in zip(devs, wants):
+            assert (from_dev(t, np.uint32) == w).all()
+
+
+# ------------------------------------------------------------------ the headline plan's depth
+
+@pytest.mark.parametrize("case", [
+    # (key type, pairs, n, L, s): Step 4 runs the same number of global merge rounds as the
+    # benchmark's 2^28 plan (8 rounds of 8-byte composites; 9 of 16-byte composites), at sizes
+    # the oracle finishes in seconds
+    (1, False, 1 << 25, 2048, 256),
+    (2, True, 1 << 24, 1024, 256),
+], ids=["u32_2p25_L2048_s256", "u64pairs_2p24_L1024_s256"])
+def test_deep_sample_merge_intermediates(ds, case):
+    kt, pairs, n, L, s = case
+    say(f"deep sample merge kt={kt} pairs={pairs} n={n} L={L} s={s}")
+    keys = synth.uniform_u32(n, 81) if kt == 1 else synth.zipf_u64(n, 82, distinct=1 << 16)
+    vals = synth.index_values(n) if pairs else None
+    fut = oracle_pool().submit(oracle.dss, keys, L, s, vals, True, False)
+    out_k, out_v, geo, ws = gpu_sort(ds, keys, vals, tuning=ds.Tuning(L, s, 0, 0, 2))
+    assert geo.levels == 2 and geo.sample_sort_global
+    ok, ov, tr = fut.result()
+    assert (out_k == ok).all()
+    if pairs:
+        assert (out_v == ov).all()
+    check_level1(geo, ws, tr, n)
+
+
 # ------------------------------------------------------------------ benchmark sizes
+
+def test_headline_2p28_uniform(ds):
+    """The benchmark's configuration: 2^28 uniform uint32 keys (seed 8) with the automatic plan
+    (L = 16384, s = 256, two levels, 2^22 samples sorted by chunk sorts and 8 merge rounds):
+    every output key and every level-1 intermediate against the oracle at the same (L, s)."""
+    n = 1 << 28
+    say("2^28 uniform u32, benchmark plan")
+    keys = synth.uniform_u32(n, 8)
+    out, _, geo, ws = gpu_sort(ds, keys)
+    assert (geo.levels, geo.sublist_len, geo.samples) == (2, 16384, 256)
+    assert geo.sample_sort_global
+    del keys
+    ok, _, tr = _heavy("2p28")
+    assert (out == ok).all()
+    check_level1(geo, ws, tr, n)
+
 
 @pytest.mark.parametrize("dist", sorted(synth.DISTRIBUTIONS_U32))
 def test_2p26_distributions(ds, dist):
-    """2^26 uint32 keys of each distribution; run twice, bit-identical (determinism)."""
+    """2^26 uint32 keys of each distribution (automatic plan): output and level-1
+    intermediates against the oracle; a second run is bit-identical (determinism)."""
     n = 1 << 26
     say(f"2^26 {dist}")
-    keys = synth.make_u32(dist, n, {"uniform": 2, "gaussian": 3, "bucket": 4, "staggered": 5,
-                                    "sorted": 6, "equal": 7}[dist])
+    keys = synth.make_u32(dist, n, C2_SEEDS[dist])
     out, _, geo, ws = gpu_sort(ds, keys)
-    assert (out == np.sort(keys)).all()
     out2, _, _, _ = gpu_sort(ds, keys)
     assert (out2 == out).all()
+    ok, _, tr = _heavy("2p26_" + dist)
+    assert (out == ok).all()
+    check_level1(geo, ws, tr, n)
 
 
-def test_2p28_uniform(ds):
-    n = 1 << 28
-    say("2^28 uniform u32")
-    keys = synth.uniform_u32(n, 8)
-    out, _, geo, ws = gpu_sort(ds, keys)
-    ref = np.sort(keys)
-    assert (out == ref).all()
-
-
-def test_2p27_u64_pairs_zipf(ds):
-    """2^27 (uint64 key, uint32 value = input index), Zipf(1.1) keys: the output is the
-    stable sort iff keys are non-decreasing, values are a permutation that maps the input keys
-    onto the output keys, and values increase inside every run of equal keys."""
+@pytest.mark.parametrize("dist", ["uniform", "zipf"])
+def test_2p27_u64_pairs(ds, dist):
+    """2^27 (uint64 key, uint32 value = input index), keys uniform (seed 9) or Zipf(1.1) over
+    2^20 values (seed 10; its top key is about 12 % of the items): keys, values and level-1
+    intermediates against the oracle's stable sort at the same (L, s)."""
     n = 1 << 27
-    say("2^27 u64 pairs zipf")
-    keys = synth.zipf_u64(n, 10)
-    vals = synth.index_values(n)
-    out_k, out_v, geo, ws = gpu_sort(ds, keys, vals)
-    assert (out_k[1:] >= out_k[:-1]).all()
-    assert (keys[out_v] == out_k).all()
-    assert (np.bincount(out_v, minlength=n) == 1).all()
-    same = out_k[1:] == out_k[:-1]
-    assert (out_v[1:][same] > out_v[:-1][same]).all()
-
-
-def test_2p27_u64_pairs_uniform(ds):
-    """2^27 (uint64 key, uint32 value = input index), uniform keys: stable sort by the same
-    properties as the Zipf case, plus equality with numpy's sort of the keys."""
-    n = 1 << 27
-    say("2^27 u64 pairs uniform")
-    keys = synth.uniform_u64(n, 11)
+    say(f"2^27 u64 pairs {dist}")
+    keys = synth.uniform_u64(n, 9) if dist == "uniform" else synth.zipf_u64(n, 10)
     vals = synth.index_values(n)
     out_k, out_v, geo, ws = gpu_sort(ds, keys, vals)
     assert geo.levels == 2
-    assert (out_k == np.sort(keys)).all()
-    assert (keys[out_v] == out_k).all()
-    assert (np.bincount(out_v, minlength=n) == 1).all()
-    same = out_k[1:] == out_k[:-1]
-    assert (out_v[1:][same] > out_v[:-1][same]).all()
+    del keys, vals
+    ok, ov, tr = _heavy("c3b_" + dist)
+    assert (out_k == ok).all() and (out_v == ov).all()
+    check_level1(geo, ws, tr, n)
 
 
 def test_two_level_f32_specials_2p25(ds):
@@ -326,9 +415,10 @@ def test_two_level_f32_specials_2p25(ds):
     bits[pos] = np.resize(np.array([0x7F800000, 0xFF800000, 0x7FC00000, 0xFFC00001,
                                     0x80000000, 0x00000000], np.uint32), pos.size)
     keys = bits.view(np.float32)
+    fut = oracle_pool().submit(oracle.stable_sort, keys)
     out, _, geo, _ = gpu_sort(ds, keys)
     assert geo.levels == 2
-    want, _ = oracle.stable_sort(keys)
+    want, _ = fut.result()
     assert (out.view(np.uint32) == want.view(np.uint32)).all()
 
 
@@ -339,19 +429,24 @@ def test_two_level_u32_pairs_duplicates_2p25(ds):
     say("2^25 u32 pairs, 256 distinct keys")
     keys = (synth.draws32(16, n) & np.uint32(0xFF)).astype(np.uint32)
     vals = synth.index_values(n)
+    fut = oracle_pool().submit(oracle.stable_sort, keys, vals)
     out_k, out_v, geo, _ = gpu_sort(ds, keys, vals)
     assert geo.levels == 2
-    want_k, want_v = oracle.stable_sort(keys, vals)
+    want_k, want_v = fut.result()
     assert (out_k == want_k).all() and (out_v == want_v).all()
 
 
 def test_two_level_u64_keys_2p26(ds):
+    """2^26 uint64 Zipf keys (seed 17), two levels: output and level-1 intermediates against
+    the oracle."""
     n = 1 << 26
     say("2^26 u64 keys two levels")
     keys = synth.zipf_u64(n, 17)
-    out, _, geo, _ = gpu_sort(ds, keys)
+    out, _, geo, ws = gpu_sort(ds, keys)
     assert geo.levels == 2
-    assert (out == np.sort(keys)).all()
+    ok, _, tr = _heavy("u64_2p26")
+    assert (out == ok).all()
+    check_level1(geo, ws, tr, n)
 
 
 def _largest_plannable(ds, kt, values):

@@ -3,15 +3,15 @@
 Every segment's result is unique (a sort, stable for key/value pairs), so the bar is bit-exact
 against ``oracle.segmented_sort`` on the same seeded input: segment sizes on both sides of every
 size-class capacity and of the one-workgroup limit, empty and one-item segments, gaps between
-segments (left untouched), float32 duplicates, signed zeros and NaNs.  At the full batched
-workload (4096 float32 segments, sizes log-uniform in [2^8, 2^20]) sampled segments are checked
-against the oracle and every segment by properties (order and an exact multiset hash)."""
+segments (left untouched), float32 duplicates, signed zeros and NaNs, up to the full batched
+workload (4096 float32 segments, sizes log-uniform in [2^8, 2^20]), where every segment is
+compared with the oracle."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from helpers import from_dev, say, to_dev, ws_view
+from helpers import from_dev, oracle_pool, oracle_segmented, say, to_dev, ws_view
 
 pytestmark = pytest.mark.gpu
 
@@ -194,7 +194,7 @@ def test_invalid_offsets_flagged(ds):
     offs = np.array([0, 100, 100_000, 150_000, 190_000], dtype=np.int64)
     out, _, _ = gpu_segmented(ds, keys, offs, max_segment=60_000, plan=plan, expect_status=32)
     for lo, hi in [(0, 100), (100_000, 150_000), (150_000, 190_000)]:
-        assert (out[lo:hi] == np.sort(keys[lo:hi])).all()
+        assert (out[lo:hi] == oracle.stable_sort(keys[lo:hi])[0]).all()
     assert (out[100:100_000] == keys[100:100_000]).all()
     assert (out[190_000:] == keys[190_000:]).all()
     # the same plan and workspace then serve a clean call normally
@@ -223,61 +223,33 @@ def test_abi_errors(ds):
     torch.cuda.synchronize()
 
 
-def _total_order_image(t):
-    """int64 image of float32 bit patterns whose integer order is IEEE totalOrder."""
-    import torch
-    b = t.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
-    neg = b >= (1 << 31)
-    return torch.where(neg, 0xFFFFFFFF - b, b + (1 << 31))
-
-
-def _segment_hash(img, seg_id, S):
-    """Per-segment multiset hash: sums of two fixed odd-multiplier mixes of every item (exact
-    int64 arithmetic modulo 2^64), so a lost, duplicated or altered item changes it."""
-    import torch
-    h1 = (img * 0x9E3779B97F4A7C15 + 0x632BE59BD9B4E019) ^ (img >> 7)
-    h2 = (img ^ 0x5851F42D4C957F2D) * 0x2545F4914F6CDD1D
-    out1 = torch.zeros(S, dtype=torch.int64, device=img.device).index_add_(0, seg_id, h1)
-    out2 = torch.zeros(S, dtype=torch.int64, device=img.device).index_add_(0, seg_id, h2)
-    return out1, out2
-
-
 @pytest.mark.timeout(600)
 def test_full_batched_workload(ds):
     """4096 float32 segments of sizes log-uniform in [2^8, 2^20] (about 5.1e8 keys), the batched
-    benchmark workload: 12 sampled segments (including the longest and shortest) bit-exact
-    against the oracle, every segment non-decreasing in totalOrder and with its multiset hash
-    unchanged."""
+    benchmark workload: every segment bit-exact against the oracle (computed on host threads
+    while the GPU sorts)."""
     import torch
     sizes = synth.segment_sizes(4096, 4, 8, 20)
     offs, n = offsets_of(sizes)
     say("[seg] full batched workload: generating", n, "keys")
     x = synth.normal_f32_segments(sizes, 4)
     S = sizes.size
+    fut = oracle_pool().submit(oracle_segmented, x, offs)
     plan = ds.Plan(3, False, n, max_segments=S)
     tk = to_dev(x)
     to = torch.from_numpy(offs).cuda()
-    seg_id = torch.repeat_interleave(torch.arange(S, device="cuda"),
-                                     torch.from_numpy(sizes).cuda())
-    before = _segment_hash(_total_order_image(tk), seg_id, S)
     ws = plan.workspace(tk.device)
     say("[seg] sorting")
     plan.sort_segmented(tk, to, max_segment=int(sizes.max()), workspace=ws)
     torch.cuda.synchronize()
     geo = plan.segmented_geometry(n, S, int(sizes.max()))
     assert int(ws_view(ws, geo.off_status, 1, np.uint32)[0]) == 0
-    img = _total_order_image(tk)
-    after = _segment_hash(img, seg_id, S)
-    assert torch.equal(before[0], after[0]) and torch.equal(before[1], after[1])
-    step_ok = (img[1:] >= img[:-1]) | (seg_id[1:] != seg_id[:-1])
-    assert bool(step_ok.all())
-    picks = {int(np.argmax(sizes)), int(np.argmin(sizes))}
-    picks |= {int(v) for v in (synth.draws64(55, 10) % np.uint64(S))}
-    for g in sorted(picks):
-        lo, hi = int(offs[g]), int(offs[g + 1])
-        want, _ = oracle.stable_sort(x[lo:hi])
-        got = tk[lo:hi].cpu().numpy().view(np.float32)
-        assert (got.view(np.uint32) == want.view(np.uint32)).all(), f"segment {g}"
+    got = from_dev(tk, np.uint32)
+    del tk, ws
+    say("[seg] waiting for the oracle")
+    want, _ = fut.result()
+    bad = np.flatnonzero(got != want.view(np.uint32))
+    assert bad.size == 0, f"{bad.size} keys differ, first at {bad[:4]}"
 
 
 def _tuning(ds, upper, L, s):
