@@ -25,6 +25,15 @@
  *  R4  n need not be a multiple of L: the last sublist is padded with items whose key is the
  *      type's maximum; under R3 they sort after every real item and are dropped at the end.
  *  R5  float32 keys are ordered by the IEEE 754 totalOrder image of their bit pattern.
+ *  R8  the randomized-splitter variant (the comparison method of Sections 1 and 3, whose
+ *      buckets come from randomly selected items): Step 3 takes the items at s random sorted
+ *      positions of each sublist instead of the chunk ends.  Sample k (0-based) of sublist i
+ *      (0-based) sits at position ((d >> 32) * L) >> 32, where d is draw i*s + k of the
+ *      SplitMix64 stream of `seed` (draw c is mix(seed + (c + 1) * 0x9E3779B97F4A7C15), mix
+ *      the generator's published finaliser); positions may repeat.  A random sample need not
+ *      be the maximum, so the last bucket is closed by +infinity instead of S[sm - 1]: bucket s
+ *      takes every item above g_{s-1}.  Every other step is unchanged; the bucket bound of
+ *      Section 4 no longer holds for this variant.
  *
  * Parity status: every function here is pinned by the CPU tests (insertion sort and exhaustive
  * small inputs, numpy's stable argsort, the bucket bound, closed forms for sorted and all-equal
@@ -142,14 +151,44 @@ int oracle_stable_sort(int kind, const void *keys_in, const uint32_t *vals_in, u
     return ORACLE_OK;
 }
 
+/* ---------------------------------------------------------------- random positions (R8) */
+
+/* Draw c of the SplitMix64 stream seeded with `seed` (Steele, Lea and Flood 2014): the state
+ * after c + 1 steps of adding the golden-ratio increment, passed through the finaliser. */
+uint64_t oracle_splitmix64(uint64_t seed, uint64_t c) {
+    uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Sorted position (in [0, L)) of random sample k of sublist i (R8). */
+static uint64_t random_position(uint64_t seed, uint64_t i, uint64_t k, uint64_t s, uint64_t L) {
+    const uint64_t d = oracle_splitmix64(seed, i * s + k);
+    return ((d >> 32) * L) >> 32;
+}
+
 /* ---------------------------------------------------------------- Algorithm 1 */
+
+int oracle_dss_sampled(int kind, const void *keys_in, const uint32_t *vals_in, uint64_t n,
+                       uint64_t L, uint64_t s, int sampling, uint64_t seed, void *keys_out,
+                       uint32_t *vals_out, oracle_trace_t *tr);
 
 /* Runs Algorithm 1 with sublist length L (= n/m) and s samples per sublist.
  * Requires L >= 1, 1 <= s <= L and s dividing L.  vals_in/vals_out/tr may be NULL. */
 int oracle_dss(int kind, const void *keys_in, const uint32_t *vals_in, uint64_t n, uint64_t L,
                uint64_t s, void *keys_out, uint32_t *vals_out, oracle_trace_t *tr) {
+    return oracle_dss_sampled(kind, keys_in, vals_in, n, L, s, 0, 0, keys_out, vals_out, tr);
+}
+
+/* Algorithm 1 with the samples of Step 3 taken at the chunk ends (sampling = 0, R1) or at
+ * random positions drawn from `seed` (sampling = 1, R8, L < 2^32). */
+int oracle_dss_sampled(int kind, const void *keys_in, const uint32_t *vals_in, uint64_t n,
+                       uint64_t L, uint64_t s, int sampling, uint64_t seed, void *keys_out,
+                       uint32_t *vals_out, oracle_trace_t *tr) {
     if (kind < ORACLE_U32 || kind > ORACLE_F32) return ORACLE_E_INVALID;
     if (L == 0 || s == 0 || s > L || L % s != 0) return ORACLE_E_INVALID;
+    if (sampling != 0 && (sampling != 1 || L >= (1ull << 32))) return ORACLE_E_INVALID;
     if (n == 0) return ORACLE_OK;
 
     /* Step 1: split A into m sublists of L items (R4: pad the last one). */
@@ -182,10 +221,11 @@ int oracle_dss(int kind, const void *keys_in, const uint32_t *vals_in, uint64_t 
     /* Step 2: sort every sublist locally (stable: ties keep input order). */
     for (uint64_t i = 0; i < m; ++i) qsort(A + i * L, L, sizeof(item_t), cmp_item);
 
-    /* Step 3: s equidistant samples per sorted sublist (R1), as composites (R3). */
+    /* Step 3: s equidistant samples per sorted sublist (R1), or s random ones (R8), as
+     * composites (R3). */
     for (uint64_t i = 0; i < m; ++i)
         for (uint64_t k = 1; k <= s; ++k) {
-            uint64_t rk = k * w - 1;
+            uint64_t rk = sampling ? random_position(seed, i, k - 1, s, L) : k * w - 1;
             S[i * s + (k - 1)].key = A[i * L + rk].key;
             S[i * s + (k - 1)].pos = i * L + rk;
         }
@@ -203,6 +243,7 @@ int oracle_dss(int kind, const void *keys_in, const uint32_t *vals_in, uint64_t 
         r[i * (s + 1)] = 0;
         for (uint64_t j = 1; j <= s; ++j) {
             uint64_t lo = 0, hi = L; /* invariant: pred(x) for x < lo, !pred(x) for x >= hi */
+            if (sampling && j == s) lo = L; /* R8: the last bucket is closed by +infinity */
             while (lo < hi) {
                 uint64_t x = lo + (hi - lo) / 2;
                 if (composite_le(A[i * L + x].key, i * L + x, g[j - 1].key, g[j - 1].pos))

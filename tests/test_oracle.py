@@ -312,3 +312,152 @@ def test_segmented_sort_definition(oracle_lib):
         oracle_lib.segmented_sort(keys, [0, 10, 5])
     with pytest.raises(ValueError):
         oracle_lib.segmented_sort(keys, [0, n + 1])
+
+
+# ------------------------------------------------------------------ randomized splitters (R8)
+#
+# The comparison method of Sections 1 and 3 builds its buckets from randomly selected items.
+# The oracle's randomized variant takes Step 3's samples at random sorted positions drawn from
+# its own SplitMix64 stream and closes the last bucket by +infinity; everything else is
+# Algorithm 1 unchanged.  Its result is still the unique sorted order; its buckets have no
+# bound.
+
+
+def test_splitmix64_published_outputs(oracle_lib):
+    """The oracle's generator and the input generator (two independent implementations of the
+    published definition) both reproduce the reference implementation's first outputs."""
+    with open(os.path.join(GOLDEN, "splitmix64_vectors.json")) as f:
+        gold = json.load(f)
+    for stream in gold["streams"]:
+        want = [int(x) for x in stream["outputs"]]
+        got = [oracle_lib.splitmix64(stream["seed"], c) for c in range(len(want))]
+        assert got == want
+        assert synth.draws64(stream["seed"], len(want)).tolist() == want
+
+
+def _random_positions(seed, m, s, L):
+    """Sample positions i*L + r of the randomized variant, computed with numpy from the input
+    generator's draws (not the oracle's): draw i*s + k, top 32 bits times L, shifted down."""
+    d = synth.draws64(seed, m * s) >> np.uint64(32)
+    r = (d * np.uint64(L)) >> np.uint64(32)
+    return r.reshape(m, s) + (np.arange(m, dtype=np.uint64) * np.uint64(L))[:, None]
+
+
+def check_random_trace(tr, keys, seed):
+    """Bookkeeping of the randomized variant: the samples are the items at the drawn positions,
+    sorted; each bucket holds exactly m samples; the last bucket is closed by +infinity; Steps
+    6-7 identities as for Algorithm 1."""
+    m, L, s = tr.m, tr.L, tr.s
+    pos = _random_positions(seed, m, s, L)
+    assert sorted(tr.sample_pos.tolist()) == sorted(pos.reshape(-1).tolist())
+    padded = np.concatenate([keys.astype(np.uint64),
+                             np.full(m * L - keys.size, np.iinfo(keys.dtype).max, np.uint64)])
+    comp = list(zip(tr.sample_key.tolist(), tr.sample_pos.tolist()))
+    assert all(a <= b for a, b in zip(comp, comp[1:]))
+    # the sample at position p holds the p-th smallest item of its sublist (stable order)
+    for i in range(m):
+        sub = np.sort(padded[i * L:(i + 1) * L], kind="stable")
+        mine = tr.sample_pos >= np.uint64(i * L)
+        mine &= tr.sample_pos < np.uint64((i + 1) * L)
+        r = (tr.sample_pos[mine] - np.uint64(i * L)).astype(np.int64)
+        assert (tr.sample_key[mine] == sub[r]).all()
+    assert (tr.count.sum(axis=1) == L).all()
+    flat_c = tr.count.T.reshape(-1)
+    flat_l = tr.offset.T.reshape(-1)
+    assert flat_l[0] == 0
+    assert (np.diff(flat_l.astype(np.int64)) == flat_c[:-1].astype(np.int64)).all()
+    assert int(flat_l[-1] + flat_c[-1]) == m * L
+    assert (tr.bucket_size == tr.count.sum(axis=0)).all()
+    # samples per bucket: bucket j < s is (g_{j-1}, g_j] with g_j = S[jm - 1]; bucket s is
+    # everything above g_{s-1}.  Each holds exactly m samples when no position was drawn twice
+    # (a repeated position repeats its sample, and equal samples share a bucket).
+    if len(set(comp)) < len(comp):
+        return
+    for j in range(s):
+        lo = comp[j * m - 1] if j else None
+        hi = comp[(j + 1) * m - 1] if j + 1 < s else None
+        inside = [c for c in comp if (lo is None or c > lo) and (hi is None or c <= hi)]
+        assert len(inside) == m
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_against_insertion_sort_small(oracle_lib, seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(1, 400))
+    L = int(2 ** rng.integers(0, 8))
+    s = int(2 ** rng.integers(0, int(np.log2(L)) + 1))
+    hi = int(rng.choice([3, 50, 1 << 32]))
+    keys = rng.integers(0, hi, size=n, dtype=np.uint64).astype(np.uint32)
+    vals = rng.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+    out_k, out_v, tr = oracle_lib.dss(keys, L, s, values=vals, trace=True, sampling=1,
+                                      seed=seed)
+    ek, ev = insertion_sort(keys.tolist(), vals.tolist())
+    assert out_k.tolist() == ek
+    assert out_v.tolist() == ev
+    check_random_trace(tr, keys, seed)
+
+
+def test_random_counts_equal_brute_force_definition(oracle_lib):
+    """a_ij of the randomized variant counted item by item: bucket j < s holds the items in
+    (g_{j-1}, g_j], bucket s every item above g_{s-1}."""
+    rng = np.random.default_rng(8)
+    for t in range(30):
+        n = int(rng.integers(1, 200))
+        L = int(2 ** rng.integers(1, 6))
+        s = int(2 ** rng.integers(0, int(np.log2(L)) + 1))
+        keys = rng.integers(0, 6, size=n).astype(np.uint32)
+        _, _, tr = oracle_lib.dss(keys, L, s, trace=True, sampling=1, seed=t)
+        m = tr.m
+        padded = keys.tolist() + [0xFFFFFFFF] * (m * L - n)
+        comp = list(zip(tr.sample_key.tolist(), tr.sample_pos.tolist()))
+        g = [comp[(j + 1) * m - 1] for j in range(s - 1)]
+        for i in range(m):
+            sub = sorted(padded[i * L:(i + 1) * L])
+            items = [(sub[r], i * L + r) for r in range(L)]
+            for j in range(s):
+                lo = g[j - 1] if j else None
+                hi = g[j] if j + 1 < s else None
+                cnt = sum(1 for it in items
+                          if (lo is None or it > lo) and (hi is None or it <= hi))
+                assert cnt == tr.count[i, j]
+
+
+@pytest.mark.parametrize("n", range(1, 7))
+def test_random_exhaustive_ternary(oracle_lib, n):
+    shapes = [(1, 1), (2, 2), (4, 2), (4, 4), (8, 2)]
+    for keys in itertools.product(range(3), repeat=n):
+        arr = np.array(keys, np.uint32)
+        expect, order = insertion_sort(keys)
+        for L, s in shapes:
+            for seed in (0, 5):
+                out, vals, tr = oracle_lib.dss(arr, L, s, values=np.arange(n, dtype=np.uint32),
+                                               trace=True, sampling=1, seed=seed)
+                assert out.tolist() == expect
+                assert vals.tolist() == order
+                check_random_trace(tr, arr, seed)
+
+
+@pytest.mark.parametrize("dist", sorted(synth.DISTRIBUTIONS_U32))
+def test_random_against_numpy_stable_argsort(oracle_lib, dist):
+    n = (1 << 16) + 123
+    keys = synth.make_u32(dist, n, 40)
+    vals = synth.index_values(n)
+    out_k, out_v, tr = oracle_lib.dss(keys, 1024, 32, values=vals, trace=True, sampling=1,
+                                      seed=77)
+    order = np.argsort(keys, kind="stable")
+    assert (out_k == keys[order]).all() and (out_v == order).all()
+    check_random_trace(tr, keys, 77)
+
+
+def test_random_buckets_have_no_bound(oracle_lib):
+    """Random samples give no bucket guarantee: with one sublist (m = 1) some seed puts more
+    than 2n'/s - m items into one bucket, which the equidistant samples never do."""
+    keys = synth.uniform_u32(64, 9)
+    L, s = 64, 8
+    worst = 0
+    for seed in range(64):
+        _, _, tr = oracle_lib.dss(keys, L, s, trace=True, sampling=1, seed=seed)
+        worst = max(worst, int(tr.bucket_size.max()))
+    assert worst > 2 * 64 // s - 1
+    _, _, tr = oracle_lib.dss(keys, L, s, trace=True)
+    assert int(tr.bucket_size.max()) <= 2 * 64 // s - 1

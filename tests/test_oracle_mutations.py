@@ -15,7 +15,7 @@ SRC = os.path.join(ROOT, "oracle", "dss_oracle.c")
 
 # (name, text in the oracle source, replacement)
 MUTANTS = [
-    ("sample_position", "uint64_t rk = k * w - 1;", "uint64_t rk = (k - 1) * w;"),
+    ("sample_position", ": k * w - 1;", ": (k - 1) * w;"),
     ("splitter_index", "g[j - 1] = S[j * m - 1];", "g[j - 1] = S[(j - 1) * m];"),
     ("rank_ties", "return key < gkey || (key == gkey && pos <= gpos);",
      "return key < gkey || (key == gkey && pos < gpos);"),
@@ -39,6 +39,14 @@ MUTANTS = [
      "return (bits & 0x80000000u) ? (bits & 0x7FFFFFFFu) : (bits | 0x80000000u);"),
     ("values_left_behind", "if (vals_out) vals_out[t] = out[t].val;",
      "if (vals_out) vals_out[t] = vals_in ? vals_in[t] : 0;"),
+    # the randomized-splitter variant (R8)
+    ("random_draw_index", "oracle_splitmix64(seed, i * s + k);",
+     "oracle_splitmix64(seed, i * s + k + 1);"),
+    ("random_position_bits", "return ((d >> 32) * L) >> 32;",
+     "return ((d & 0xFFFFFFFFull) * L) >> 32;"),
+    ("random_last_bucket_open", "if (sampling && j == s) lo = L;", ""),
+    ("splitmix_finaliser_shift", "z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;",
+     "z = (z ^ (z >> 29)) * 0x94D049BB133111EBull;"),
 ]
 
 
