@@ -50,13 +50,30 @@ enum {
  *                  power of two dividing L;
  *  sublist_len2, samples2: the same for the second level (Step 9 run as a segmented sort);
  *  levels       0 = auto, 1 = force one level (Step 9 sorts each bucket in one workgroup),
- *               2 = force two levels. */
+ *               2 = force two levels;
+ *  sampling     0 = Algorithm 1 (Step 3 takes the last item of each of the s chunks of a
+ *               sorted sublist, which bounds every bucket, Section 4); 1 = the randomized-
+ *               splitter comparison method of Sections 1 and 3: Step 3 of the first level
+ *               takes the items at s random sorted positions instead (sample k of sublist i at
+ *               ((d >> 32) * L) >> 32, d = draw i*s + k of the SplitMix64 stream of `seed`,
+ *               positions may repeat) and the last bucket is closed by +infinity.  Nothing
+ *               then bounds a bucket: a first-level bucket larger than what its second step can
+ *               take (one workgroup, or the second level's sublist count) is moved to its place
+ *               as a contiguous range (Step 8) and sorted afterwards by a further run of
+ *               Algorithm 1 (deterministic samples) on that range.  Finding such buckets costs
+ *               one device-to-host read per call, so a randomized call waits for its own
+ *               kernels (it synchronises `stream`) and cannot be captured into a graph.  The
+ *               result is the same unique sorted order.  Plain sorts only (dsort_keys,
+ *               dsort_pairs);
+ *  seed         the randomized variant's stream seed. */
 typedef struct {
     uint32_t sublist_len;
     uint32_t samples;
     uint32_t sublist_len2;
     uint32_t samples2;
     uint32_t levels;
+    uint32_t sampling;
+    uint64_t seed;
 } dsort_tuning_t;
 
 typedef struct dsort_plan_s *dsort_plan_t;
@@ -123,6 +140,13 @@ typedef struct {
     uint64_t off_offsets;         /* l_ij (Step 7) */
     uint64_t off_buckets;         /* level-1 buckets as uint32 {begin, size, first piece, pieces} */
     uint64_t workspace_bytes;     /* bytes this n needs (<= the plan's workspace size) */
+    /* Randomized sampling (tuning.sampling = 1) only, else 0: first-level buckets with more
+     * than bucket_limit items skip the second step and are sorted by a further run; their
+     * count (uint32) and their bucket indices (uint32 each) after a call. */
+    uint32_t sampling;
+    uint32_t bucket_limit;
+    uint64_t off_overflow_count;
+    uint64_t off_overflow_list;
 } dsort_geometry_t;
 
 int dsort_plan_geometry(dsort_plan_t plan, uint64_t n, dsort_geometry_t *out);
@@ -157,7 +181,7 @@ int dsort_plan_geometry(dsort_plan_t plan, uint64_t n, dsort_geometry_t *out);
  * bucket sorts then share the side streams.
  * Errors: DSORT_E_INVALID (bad plan or pointer, misalignment, values given to a keys-only plan
  * or missing for a pairs plan, n or num_segments above the plan's), DSORT_E_UNSUPPORTED
- * (max_segment above segment_limit), DSORT_E_HIP.  n = 0 or num_segments = 0 is a no-op. */
+ * (max_segment above segment_limit, or a plan with randomized sampling), DSORT_E_HIP.  n = 0 or num_segments = 0 is a no-op. */
 int dsort_segmented(dsort_plan_t plan, void *d_keys, uint32_t *d_values, uint64_t n,
                     const uint64_t *d_offsets, uint64_t num_segments, uint64_t max_segment,
                     void *d_workspace, void *stream);

@@ -42,9 +42,12 @@ class DsortError(RuntimeError):
 
 
 class Tuning(ctypes.Structure):
+    """dsort_tuning_t: (L, s) per level, forced level count, and ``sampling`` = 1 with ``seed``
+    for the randomized-splitter comparison method (0 = Algorithm 1's chunk-end samples)."""
     _fields_ = [("sublist_len", ctypes.c_uint32), ("samples", ctypes.c_uint32),
                 ("sublist_len2", ctypes.c_uint32), ("samples2", ctypes.c_uint32),
-                ("levels", ctypes.c_uint32)]
+                ("levels", ctypes.c_uint32), ("sampling", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64)]
 
 
 class _Geometry(ctypes.Structure):
@@ -57,7 +60,9 @@ class _Geometry(ctypes.Structure):
                 ("off_status", ctypes.c_uint64), ("off_samples", ctypes.c_uint64),
                 ("off_sorted_samples", ctypes.c_uint64), ("off_counts", ctypes.c_uint64),
                 ("off_offsets", ctypes.c_uint64), ("off_buckets", ctypes.c_uint64),
-                ("workspace_bytes", ctypes.c_uint64)]
+                ("workspace_bytes", ctypes.c_uint64), ("sampling", ctypes.c_uint32),
+                ("bucket_limit", ctypes.c_uint32), ("off_overflow_count", ctypes.c_uint64),
+                ("off_overflow_list", ctypes.c_uint64)]
 
 
 class _SegGeometry(ctypes.Structure):
@@ -200,6 +205,10 @@ class Geometry:
     off_offsets: int
     off_buckets: int
     workspace_bytes: int
+    sampling: int
+    bucket_limit: int
+    off_overflow_count: int
+    off_overflow_list: int
 
 
 @dataclass

@@ -45,6 +45,12 @@ struct Geom {
     uint32_t L2 = 0, s2 = 0, m2max = 0, tiles2max = 0;
     uint32_t final_buckets = 0;
     uint32_t plan_rule = 0;  // which rule chose (s1, s2): 0 preferred, 1 smallest feasible
+    // randomized samples at level 1 (the comparison method): no bucket bound, so level-1
+    // buckets of more than bucket_limit real items skip Step 9's normal path and are sorted by
+    // a further deterministic run afterwards
+    bool random = false;
+    uint64_t seed = 0;
+    uint32_t bucket_limit = 0;
 
     // workspace byte offsets
     size_t o_status = 0, o_wkeys = 0, o_wvals = 0;
@@ -53,8 +59,13 @@ struct Geom {
     size_t o_buckets1 = 0, o_tileoff2 = 0;
     size_t o_samp2 = 0, o_samp2_sorted = 0, o_counts2 = 0, o_offs2 = 0, o_pdst2 = 0, o_psrc2 = 0;
     size_t o_final = 0, o_lists = 0;
+    size_t o_ovf = 0;  // randomized: the level-1 buckets routed to the further run
     size_t total = 0;
 };
+
+// Word of the workspace's status page that counts the level-1 buckets of a randomized call
+// routed to the further run (cleared by the pipeline's first kernel).
+constexpr uint32_t kOverflowWord = 40;
 
 // Segmented sorts: segments of at most small_cap items are sorted as one-piece buckets; the
 // longer ones are split by length into classes (lengths in (lo, hi]), each running one level of

@@ -28,6 +28,7 @@
 
 #include <map>
 #include <mutex>
+#include <vector>
 
 #include "dsort_internal.h"
 
@@ -155,6 +156,19 @@ template <> struct Tr<uint64_t, true> {
 template <class K> struct KeyMax;
 template <> struct KeyMax<uint32_t> { static constexpr uint32_t v = 0xFFFFFFFFu; };
 template <> struct KeyMax<uint64_t> { static constexpr uint64_t v = ~0ull; };
+
+// Position part i*L + r of a sample composite.
+__device__ __forceinline__ uint32_t samp_pos(uint64_t c) { return (uint32_t)c; }
+__device__ __forceinline__ uint32_t samp_pos(const C128 &c) { return c.pos; }
+
+// Draw c of the SplitMix64 stream of `seed` (Steele, Lea and Flood 2014): the state after c + 1
+// golden-ratio increments, through the published finaliser.  Randomized samples only.
+__device__ __forceinline__ uint64_t splitmix64_draw(uint64_t seed, uint64_t c) {
+    uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
 
 // ------------------------------------------------------------------------------ segments
 
@@ -666,6 +680,8 @@ struct TileArgs {
     uint32_t *status;
     const uint32_t *pdst;  // GIN: bucket-major destinations l_ij of the previous level's pieces
     const uint32_t *psrc;  // GIN: their source positions in src_keys / src_vals
+    uint64_t seed;         // MODE_SAMPLE without GIN, random != 0: the samples' stream seed
+    uint32_t random;       // 1: Step 3 takes s random sorted positions instead of chunk ends
 };
 
 // Sublists of a second level read straight from the pieces of the first (Step 8 of the first
@@ -801,6 +817,8 @@ __global__ __launch_bounds__(CAP / E) void k_tile(TileArgs a) {
     static_assert(!GIN || (MODE == MODE_SAMPLE && !XIN), "piece gathers feed Steps 1-3 only");
     __shared__ T lds[lds_elems<T>(CAP) + 1];
     __shared__ uint32_t tb[GIN ? kTilePieces + 1 : 1], sb[GIN ? kTilePieces : 1], pr[2];
+    constexpr bool kCanRandom = MODE == MODE_SAMPLE && !GIN;
+    __shared__ uint32_t rp[kCanRandom ? 1024 : 1];  // randomized samples: (position, k) keys
     const uint32_t tid = threadIdx.x;
     const uint32_t bd = blockDim.x;
 
@@ -856,11 +874,29 @@ __global__ __launch_bounds__(CAP / E) void k_tile(TileArgs a) {
     block_sort<T, E, V>(lds, P);  // key/value elements carry their load position
 
     if (MODE == MODE_SAMPLE) {
-        typename R::SC *smp = (typename R::SC *)a.samples;
-        const uint32_t w = a.L / a.s;
-        for (uint32_t k = tid; k < a.s; k += bd) {
-            const uint32_t r = (k + 1) * w - 1;
-            smp[(size_t)(loc.tile0 + loc.i) * a.s + k] = R::samp(R::key(lds[pidx<T>(r)]), loc.i * a.L + r);
+        typename R::SC *smp = (typename R::SC *)a.samples + (size_t)(loc.tile0 + loc.i) * a.s;
+        if (kCanRandom && a.random) {
+            // Randomized variant: sample k sits at sorted position ((d >> 32) * L) >> 32, d the
+            // draw i*s + k.  The samples are written in position order (ties by k), so that each
+            // sublist's samples stay a sorted run for Step 4 and for the rank bisection.
+            for (uint32_t k = tid; k < a.s; k += bd) {
+                const uint64_t d = splitmix64_draw(a.seed, (uint64_t)loc.i * a.s + k);
+                rp[k] = (__umulhi((uint32_t)(d >> 32), a.L) << 10) | k;  // L <= 2^16, s <= 2^10
+            }
+            __syncthreads();
+            for (uint32_t k = tid; k < a.s; k += bd) {
+                const uint32_t me = rp[k];
+                uint32_t rank = 0;
+                for (uint32_t q = 0; q < a.s; ++q) rank += rp[q] < me ? 1u : 0u;
+                const uint32_t r = me >> 10;
+                smp[rank] = R::samp(R::key(lds[pidx<T>(r)]), loc.i * a.L + r);
+            }
+        } else {
+            const uint32_t w = a.L / a.s;
+            for (uint32_t k = tid; k < a.s; k += bd) {
+                const uint32_t r = (k + 1) * w - 1;
+                smp[k] = R::samp(R::key(lds[pidx<T>(r)]), loc.i * a.L + r);
+            }
         }
     }
 
@@ -1055,7 +1091,8 @@ __device__ __forceinline__ void rank_chunks(const K *keys, const typename Tr<K, 
 template <class K, bool V>
 __global__ __launch_bounds__(256) void k_rank(const K *keys, const void *sorted_samples,
                                               const void *tile_samples, uint32_t *counts,
-                                              SegView sv, uint32_t L, uint32_t s) {
+                                              SegView sv, uint32_t L, uint32_t s,
+                                              uint32_t random) {
     using R = Tr<K, V>;
     using SC = typename R::SC;
     __shared__ uint32_t rk[1025], chunk[1024];
@@ -1070,6 +1107,36 @@ __global__ __launch_bounds__(256) void k_rank(const K *keys, const void *sorted_
     __syncthreads();
     const uint32_t p0 = loc.i * L;
     const uint32_t w = L / s;
+    if (random) {
+        // Randomized samples (sorted run, at arbitrary positions): if c of them are <= g_j, the
+        // rank lies after the position of sample c - 1 and at or before that of sample c, and is
+        // bisected there in global memory.  +infinity closes the last bucket: r_is = L.
+        for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) {
+            if (j + 1 == s) {
+                rk[s] = L;
+                continue;
+            }
+            const SC g = S[(size_t)(j + 1) * loc.m - 1];
+            uint32_t lo = 0, hi = s;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (!lt(g, ts[mid])) lo = mid + 1; else hi = mid;
+            }
+            uint32_t a = lo ? samp_pos(ts[lo - 1]) - p0 + 1 : 0u;
+            uint32_t b = lo < s ? samp_pos(ts[lo]) - p0 : L;
+            while (a < b) {
+                const uint32_t x = (a + b) >> 1;
+                const K kx = x < count ? keys[base + x] : KeyMax<K>::v;
+                if (!lt(g, R::samp(kx, p0 + x))) a = x + 1; else b = x;
+            }
+            rk[j + 1] = a;
+        }
+        if (threadIdx.x == 0) rk[0] = 0;
+        __syncthreads();
+        uint32_t *row = counts + (size_t)(loc.tile0 + loc.i) * s;
+        for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) row[j] = rk[j + 1] - rk[j];
+        return;
+    }
     for (uint32_t j = threadIdx.x; j < s; j += blockDim.x) {
         const SC g = S[(size_t)(j + 1) * loc.m - 1];
         uint32_t lo = 0, hi = s;  // c = #{k : sample_k <= g}
@@ -1151,11 +1218,15 @@ struct Classes {
 // overlap with [0, seg_size) (several trailing buckets may hold pads when the last sublist is
 // mostly padding).  When asked, also the tile map of the next level: ceil(size / L_next)
 // tiles per bucket, exclusive prefix, s + 1 entries.  `bucket0` is the global index of the
-// segment's first bucket (for the class work lists).
+// segment's first bucket (for the class work lists).  A bucket of more than `limit` real items
+// (randomized samples only; Algorithm 1's bound keeps every bucket within it) gets no tiles
+// and no class: it is appended to `ovf_list` (count in *ovf_count) for a further run.
 __device__ void emit_buckets(const uint32_t *colsum, const uint32_t *colbase, uint32_t s,
                              uint32_t seg_begin, uint32_t seg_size, uint32_t piece0, uint32_t m,
                              uint4 *buckets, uint32_t *tile_off_next, uint32_t L_next,
-                             uint32_t *tmp, const Classes &cls, uint32_t bucket0) {
+                             uint32_t *tmp, const Classes &cls, uint32_t bucket0,
+                             uint32_t limit = 0xFFFFFFFFu, uint32_t *ovf_count = nullptr,
+                             uint32_t *ovf_list = nullptr) {
     __shared__ uint32_t ccount[kMaxClasses], cbase[kMaxClasses];
     if (threadIdx.x < (uint32_t)kMaxClasses) ccount[threadIdx.x] = 0;
     __syncthreads();
@@ -1168,8 +1239,10 @@ __device__ void emit_buckets(const uint32_t *colsum, const uint32_t *colbase, ui
         const uint32_t b = colbase[j];
         const uint32_t size = b >= seg_size ? 0u : min(colsum[j], seg_size - b);
         buckets[j] = make_uint4(seg_begin + b, size, piece0 + j * m, m);
-        if (tile_off_next) tmp[j] = (size + L_next - 1) / L_next;
-        if (cls.n && size) {
+        const bool over = size > limit && ovf_list;
+        if (over) ovf_list[atomicAdd(ovf_count, 1u)] = bucket0 + j;  // at most s entries
+        if (tile_off_next) tmp[j] = over ? 0u : (size + L_next - 1) / L_next;
+        if (cls.n && size && !over) {
             uint32_t c = 0;
             while (c + 1 < cls.n && cls.cap[c] < size) ++c;
             mycls[r] = c;
@@ -1298,7 +1371,8 @@ __global__ __launch_bounds__(256) void k_scan_partial(const uint32_t *counts, ui
 __global__ __launch_bounds__(1024) void k_scan_mid(uint32_t *partial, uint32_t nrb, uint32_t m,
                                                    uint32_t s, uint32_t n, uint4 *buckets,
                                                    uint32_t *tile_off_next, uint32_t L_next,
-                                                   Classes cls) {
+                                                   Classes cls, uint32_t limit,
+                                                   uint32_t *ovf_count, uint32_t *ovf_list) {
     __shared__ uint32_t colsum[1024], colbase[1024], tmp[1024];
     const uint32_t ng = blockDim.x / s;  // s divides blockDim (both powers of two, s <= 1024)
     const uint32_t grp = threadIdx.x / s, j = threadIdx.x % s;
@@ -1322,7 +1396,8 @@ __global__ __launch_bounds__(1024) void k_scan_mid(uint32_t *partial, uint32_t n
         run += x;
     }
     lds_scan(colbase, s);  // (starts with a barrier: tmp is free again after it)
-    emit_buckets(colsum, colbase, s, 0u, n, 0u, m, buckets, tile_off_next, L_next, tmp, cls, 0u);
+    emit_buckets(colsum, colbase, s, 0u, n, 0u, m, buckets, tile_off_next, L_next, tmp, cls, 0u,
+                 limit, ovf_count, ovf_list);
 }
 
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t *counts, const uint32_t *partial,
@@ -1498,9 +1573,11 @@ __global__ __launch_bounds__((CAP / GatherE<K, V, CAP>::E), (GatherE<K, V, CAP>:
 
 // The workspace's first 256 bytes: [0] status flags, [1, 1 + kMaxClasses) the final buckets'
 // class counters, [1 + kMaxClasses, 1 + 2 kMaxClasses) those of a segmented sort's one-piece
-// buckets, and 2 kMaxClasses entries after each counter its class's work-queue counter.
+// buckets, 2 kMaxClasses entries after each counter its class's work-queue counter, and at
+// kOverflowWord the count of a randomized call's buckets routed to a further run.
+static_assert(kOverflowWord > 4u * kMaxClasses && kOverflowWord < 64u, "status page layout");
 __global__ void k_init(uint32_t *status) {
-    if (threadIdx.x <= 4u * kMaxClasses && blockIdx.x == 0) status[threadIdx.x] = 0;
+    if (threadIdx.x < 64u && blockIdx.x == 0) status[threadIdx.x] = 0;
 }
 
 // Long-segment classes of a segmented sort, as the set-up kernel sees them.
@@ -1592,6 +1669,62 @@ __global__ __launch_bounds__(1024) void k_seg_prepare(const uint64_t *off, uint3
         }
 }
 
+// Step 8 as the paper states it, for the level-1 buckets of a randomized call that are routed
+// to a further run: every piece A_ij of every listed bucket is copied from the sorted sublists
+// (src) to its place l_ij in dst, clipped to the bucket's real items (pads, the largest items,
+// sit at the end of the last piece and are dropped).  One wave per piece, grid-stride over
+// (listed bucket, piece); xout applies the f32 order map's inverse on the way.
+template <class K>
+__global__ __launch_bounds__(256) void k_reloc_listed(const K *src, K *dst, const uint32_t *src_vals,
+                                                      uint32_t *dst_vals, const uint4 *buckets,
+                                                      const uint32_t *pdst, const uint32_t *psrc,
+                                                      const uint32_t *ovf_count,
+                                                      const uint32_t *ovf_list, uint32_t s,
+                                                      uint32_t m, uint32_t n_total,
+                                                      uint32_t xout) {
+    const uint32_t nb = min(*ovf_count, s);
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t nwave = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t q = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+         q < (uint64_t)nb * m; q += nwave) {
+        const uint32_t bi = (uint32_t)(q / m), p = (uint32_t)(q % m);
+        const uint4 b = buckets[ovf_list[bi]];
+        if (p >= b.w) continue;
+        const uint32_t end = min(b.x + b.y, n_total);
+        const uint32_t d0 = min(pdst[b.z + p], end);
+        const uint32_t d1 = min(p + 1 < b.w ? pdst[b.z + p + 1] : end, end);
+        const uint32_t s0 = psrc[b.z + p];
+        for (uint32_t x = lane; d0 + x < d1 && s0 + x < n_total; x += 64) {
+            K k = src[s0 + x];
+            if (xout) k = (K)f32_out((uint32_t)k);
+            dst[d0 + x] = k;
+            if (dst_vals) dst_vals[d0 + x] = src_vals[s0 + x];
+        }
+    }
+}
+
+// Copies the listed buckets' ranges [begin, begin + size) from src to dst (randomized calls of
+// two levels: their relocated items move from the workspace copy back into the keys).
+template <class K>
+__global__ __launch_bounds__(256) void k_copy_listed(const K *src, K *dst, const uint32_t *src_vals,
+                                                     uint32_t *dst_vals, const uint4 *buckets,
+                                                     const uint32_t *ovf_count,
+                                                     const uint32_t *ovf_list, uint32_t s,
+                                                     uint32_t n_total, uint32_t xout) {
+    const uint32_t nb = min(*ovf_count, s);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t bi = 0; bi < nb; ++bi) {
+        const uint4 b = buckets[ovf_list[bi]];
+        const uint32_t end = min(b.x + b.y, n_total);
+        for (uint32_t x = b.x + blockIdx.x * blockDim.x + threadIdx.x; x < end; x += stride) {
+            K k = src[x];
+            if (xout) k = (K)f32_out((uint32_t)k);
+            dst[x] = k;
+            if (dst_vals) dst_vals[x] = src_vals[x];
+        }
+    }
+}
+
 // Clears the work-list counters of the final buckets and their queue counters (between the
 // classes of a segmented sort).
 __global__ void k_clear_counters(uint32_t *count, uint32_t n) {
@@ -1665,6 +1798,7 @@ template <> struct ClassCaps<C128> {
 };
 
 constexpr uint32_t kNumCUs = 256;
+constexpr uint32_t kListedGrid = 1024;  // workgroups of the listed-bucket copies
 
 // Side streams on which the bucket size classes of one call run side by side, so that the
 // single-bucket latency of a sparsely used class and the tail of a busy one overlap other
@@ -1928,7 +2062,7 @@ template <class K, bool V, bool F32> struct Pipeline {
             if (rc) return rc;
             DS_LAUNCH("s56_rank", (k_rank<K, V>), dim3(q.tiles_max), dim3(256),
                       (const K *)wkeys, (const void *)sorted, (const void *)samp, counts, sv,
-                      q.L, q.s);
+                      q.L, q.s, 0u);
             DS_LAUNCH("s7_scan", k_scan_seg, dim3(q.gmax), dim3(256), (const uint32_t *)counts,
                       offs, pdst, psrc, sv, q.L, q.s, finals, fcls);
             GatherArgs a{wkeys, keys, wvals, d_vals, finals, pdst, psrc, fcls.count, lists,
@@ -1972,9 +2106,17 @@ template <class K, bool V, bool F32> struct Pipeline {
         K *tiles = g.levels == 1 ? wkeys : keys;
         uint32_t *tvals = g.levels == 1 ? wvals : d_vals;
 
+        // Randomized samples (level 1 only): buckets beyond bucket_limit are listed here and
+        // relocated as contiguous ranges for a further run (run_pipeline).
+        const uint32_t rnd = g.random ? 1u : 0u;
+        uint32_t *ovf_count = rnd ? status + kOverflowWord : nullptr;
+        uint32_t *ovf_list = rnd ? (uint32_t *)(ws + g.o_ovf) : nullptr;
+        const uint32_t limit = rnd ? g.bucket_limit : 0xFFFFFFFFu;
+
         // Steps 1-3
         {
-            TileArgs a{keys, tiles, d_vals, tvals, sv1, g.L1, g.s1, samp, status};
+            TileArgs a{keys, tiles, d_vals, tvals, sv1, g.L1, g.s1, samp, status, nullptr,
+                       nullptr, g.seed, rnd};
             DS_LAUNCH("s123_local_sort", (k_tile<K, V, TE, TCAP, MODE_SAMPLE, F32, false>),
                       dim3(g.m1), dim3(g.L1 / TE), a);
         }
@@ -1985,7 +2127,7 @@ template <class K, bool V, bool F32> struct Pipeline {
         if (rc) return rc;
         // Steps 5-6
         DS_LAUNCH("s56_rank", (k_rank<K, V>), dim3(g.m1), dim3(256), (const K *)tiles,
-                  (const void *)sorted, (const void *)samp, counts, sv1, g.L1, g.s1);
+                  (const void *)sorted, (const void *)samp, counts, sv1, g.L1, g.s1, rnd);
         // Step 7
         DS_LAUNCH("s7_scan_colsum", k_scan_partial, dim3(g.scan_nrb), dim3(256),
                   (const uint32_t *)counts, partial, g.m1, g.s1, g.scan_rb);
@@ -1993,10 +2135,21 @@ template <class K, bool V, bool F32> struct Pipeline {
         const Classes cls = classes(status, lists, g.final_buckets);
         Classes none{};
         DS_LAUNCH("s7_scan_mid", k_scan_mid, dim3(1), dim3(1024), partial, g.scan_nrb, g.m1,
-                  g.s1, n, buckets1, tileoff2, g.L2, g.levels == 1 ? cls : none);
+                  g.s1, n, buckets1, tileoff2, g.L2, g.levels == 1 ? cls : none, limit,
+                  ovf_count, ovf_list);
         DS_LAUNCH("s7_scan_update", k_scan_apply, dim3(g.scan_nrb), dim3(256),
                   (const uint32_t *)counts, (const uint32_t *)partial, (const uint4 *)buckets1,
                   offs, pdst, psrc, g.m1, g.s1, g.scan_rb, g.L1);
+        if (rnd) {
+            // one level: the listed buckets go straight to their places in keys; two levels:
+            // to the workspace copy, which the second level fills only at the other buckets
+            DS_LAUNCH("s8_reloc_listed", (k_reloc_listed<K>), dim3(kListedGrid), dim3(256),
+                      (const K *)tiles, g.levels == 1 ? keys : wkeys, tvals,
+                      V ? (g.levels == 1 ? d_vals : wvals) : nullptr, (const uint4 *)buckets1,
+                      (const uint32_t *)pdst, (const uint32_t *)psrc,
+                      (const uint32_t *)ovf_count, (const uint32_t *)ovf_list, g.s1, g.m1, n,
+                      (g.levels == 1 && F32) ? 1u : 0u);
+        }
 
         if (g.levels == 1) {
             // Steps 8-9 fused: gather every bucket's pieces, merge them, write into keys.
@@ -2026,12 +2179,18 @@ template <class K, bool V, bool F32> struct Pipeline {
                           tm, "l2_s4_sample_sort", "l2_s4_sample_merge");
         if (rc) return rc;
         DS_LAUNCH("l2_s56_rank", (k_rank<K, V>), dim3(g.tiles2max), dim3(256), (const K *)wkeys,
-                  (const void *)sorted2, (const void *)samp2, counts2, sv2, g.L2, g.s2);
+                  (const void *)sorted2, (const void *)samp2, counts2, sv2, g.L2, g.s2, 0u);
         DS_LAUNCH("l2_s7_scan", k_scan_seg, dim3(g.s1), dim3(256), (const uint32_t *)counts2,
                   offs2, pdst2, psrc2, sv2, g.L2, g.s2, finals, cls);
         GatherArgs a{wkeys, keys, wvals, d_vals, finals, pdst2, psrc2, status + 1, lists,
                      g.final_buckets, n, status};
-        return launch_classes(a, st, tm, false);
+        rc = launch_classes(a, st, tm, false);
+        if (rc || !rnd) return rc;
+        DS_LAUNCH("s8_copy_listed", (k_copy_listed<K>), dim3(kListedGrid), dim3(256),
+                  (const K *)wkeys, keys, (const uint32_t *)wvals, V ? d_vals : nullptr,
+                  (const uint4 *)buckets1, (const uint32_t *)ovf_count,
+                  (const uint32_t *)ovf_list, g.s1, n, F32 ? 1u : 0u);
+        return DSORT_OK;
     }
 };
 
@@ -2164,13 +2323,8 @@ int run_segmented(const SegGeom &g, void *d_keys, uint32_t *d_vals, const uint64
     }
 }
 
-int run_pipeline(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, void *stream,
-                 Timing *tm) {
-    hipStream_t st = (hipStream_t)stream;
-    if (g.levels < 0) return DSORT_OK;
-    (void)hipGetLastError();  // do not attribute an earlier caller's error to this call
-    if (g.n > 0xFFFFFFFFull) return DSORT_E_INVALID;
-    if (tm && !tm->enabled) tm = nullptr;
+static int run_geom(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, hipStream_t st,
+                    Timing *tm) {
     switch (g.key_type) {
         case DSORT_U32:
             return g.values ? Pipeline<uint32_t, true, false>::run(g, d_keys, d_vals, d_ws, st, tm)
@@ -2184,6 +2338,73 @@ int run_pipeline(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, void
         default:
             return DSORT_E_INVALID;
     }
+}
+
+__global__ void k_set_word(uint32_t *p, uint32_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// The further run of a randomized call: reads back the level-1 buckets that the pipeline routed
+// past its normal path (already relocated, unsorted, to their final ranges in the keys) and
+// sorts each range in place with the deterministic automatic plan, in the same workspace (the
+// caller sized it for that).  Waits for the stream once, plus once more when buckets were
+// routed.  A call whose kernels raised status flags is left as it is (the flags stay for the
+// caller); after further runs the status page holds their flags and the routed-bucket count.
+static int finish_random(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws,
+                         hipStream_t st, Timing *tm) {
+    const char *ws = (const char *)d_ws;
+    uint32_t page[64];
+    if (hipMemcpyAsync(page, ws + g.o_status, sizeof(page), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return record_error("random_readback", hipGetLastError());
+    const uint32_t cnt = page[kOverflowWord];
+    if (cnt == 0 || page[0] != 0) return DSORT_OK;
+    if (cnt > g.s1) return record_error("random_readback", hipErrorInvalidValue);
+    std::vector<uint32_t> list(cnt);
+    std::vector<uint4> table(g.s1);
+    if (hipMemcpyAsync(list.data(), ws + g.o_ovf, 4ull * cnt, hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(table.data(), ws + g.o_buckets1, sizeof(uint4) * g.s1,
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return record_error("random_readback", hipGetLastError());
+    const size_t kb = g.caps.key_bytes;
+    for (uint32_t b : list) {
+        if (b >= g.s1) return record_error("random_readback", hipErrorInvalidValue);
+        const uint4 d = table[b];
+        if ((uint64_t)d.x + d.y > g.n) return record_error("random_readback", hipErrorInvalidValue);
+        Geom h;
+        const dsort_tuning_t automatic{};
+        int rc = make_geom(g.key_type, g.values, d.y, automatic, h);
+        if (rc != DSORT_OK) return rc;
+        if (h.levels < 0) continue;
+        rc = run_geom(h, (char *)d_keys + kb * d.x, d_vals ? d_vals + d.x : nullptr, d_ws, st, tm);
+        if (rc != DSORT_OK) return rc;
+    }
+    hipLaunchKernelGGL(k_set_word, dim3(1), dim3(64), 0, st,
+                       (uint32_t *)((char *)d_ws + g.o_status) + kOverflowWord, cnt);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? DSORT_OK : record_error("random_count", e);
+}
+
+int run_pipeline(const Geom &g, void *d_keys, uint32_t *d_vals, void *d_ws, void *stream,
+                 Timing *tm) {
+    hipStream_t st = (hipStream_t)stream;
+    if (g.levels < 0) return DSORT_OK;
+    (void)hipGetLastError();  // do not attribute an earlier caller's error to this call
+    if (g.n > 0xFFFFFFFFull) return DSORT_E_INVALID;
+    if (tm && !tm->enabled) tm = nullptr;
+    if (g.random) {
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) {
+            (void)hipGetLastError();
+            return DSORT_E_UNSUPPORTED;  // the further run needs a read-back
+        }
+    }
+    const int rc = run_geom(g, d_keys, d_vals, d_ws, st, tm);
+    if (rc != DSORT_OK || !g.random) return rc;
+    return finish_random(g, d_keys, d_vals, d_ws, st, tm);
 }
 
 }  // namespace dsort

@@ -81,7 +81,7 @@ int make_geom(int key_type, bool values, uint64_t n, const dsort_tuning_t &tu, G
         return DSORT_OK;
     }
     const bool tuned = tu.sublist_len || tu.samples || tu.sublist_len2 || tu.samples2 || tu.levels;
-    if (tu.levels > 2) return DSORT_E_UNSUPPORTED;
+    if (tu.levels > 2 || tu.sampling > 1) return DSORT_E_UNSUPPORTED;
     if (!tuned && n <= c.final_cap) {
         g.levels = 0;
         g.total = off;
@@ -179,6 +179,23 @@ int make_geom(int key_type, bool values, uint64_t n, const dsort_tuning_t &tu, G
         g.tiles2max = (uint32_t)(ceil_div(n, L2) + s1);
         g.final_buckets = (uint32_t)(s1 * s2);
     }
+    if (tu.sampling == 1) {
+        // Randomized samples bound no bucket.  The normal path takes a level-1 bucket of up to
+        // one workgroup (one level), or of as many level-2 sublists as the level-2 sample sort
+        // and bucket capacity allow with this s2 (two levels; the level-2 grid, ceil(n/L2) + s1
+        // tiles, covers any split of n into s1 buckets).
+        g.random = true;
+        g.seed = tu.seed;
+        if (one) {
+            g.bucket_limit = c.final_cap;
+        } else {
+            uint64_t mm = 0;
+            while (mm < kMaxPieces && (mm + 1) * s2 <= c.samp_cap &&
+                   bucket_bound(mm + 1, L2, s2) <= c.final_cap)
+                ++mm;
+            g.bucket_limit = (uint32_t)std::min<uint64_t>(mm * L2, 0xFFFFFFFFull);
+        }
+    }
 
     // --- workspace map
     auto take = [&](size_t bytes) {
@@ -211,6 +228,7 @@ int make_geom(int key_type, bool values, uint64_t n, const dsort_tuning_t &tu, G
         g.o_final = g.o_buckets1;
     }
     g.o_lists = take((size_t)kNumClasses * g.final_buckets * 4);
+    if (g.random) g.o_ovf = take(s1 * 4);
     g.total = off;
     return DSORT_OK;
 }
@@ -404,6 +422,42 @@ static int geom_for(dsort_plan_s *p, uint64_t n, const Geom **out) {
     return DSORT_OK;
 }
 
+// Raises `ws` to the largest workspace any n in [2, max_items] needs under `tu`.  The geometry
+// is piecewise in n: on each interval where (levels, rule, s1, s2, sample-sort and scan variants)
+// stay fixed, every buffer grows with n, and these pieces never recur once left (the level
+// count and the rule only grow with n, and so do s1 and s2 under one rule).  So the largest
+// footprint is at the right end of some piece; walk the pieces, finding each right end by
+// bisection.
+static int workspace_walk(int key_type, bool values, uint64_t max_items, const dsort_tuning_t &tu,
+                          size_t &ws) {
+    if (max_items < 2) return DSORT_OK;
+    auto key = [](const Geom &h) {
+        return ((uint64_t)(h.levels + 1) << 56) ^ ((uint64_t)h.plan_rule << 52) ^
+               ((uint64_t)h.s1 << 36) ^ ((uint64_t)h.s2 << 12) ^
+               ((uint64_t)h.samp_global << 1) ^ (uint64_t)h.scan_large;
+    };
+    uint64_t lo = 2;
+    while (lo <= max_items) {
+        Geom h;
+        if (dsort::make_geom(key_type, values, lo, tu, h) != DSORT_OK) return DSORT_E_UNSUPPORTED;
+        const uint64_t k0 = key(h);
+        uint64_t a = lo, b = max_items;
+        while (a < b) {
+            const uint64_t mid = a + (b - a + 1) / 2;
+            Geom t;
+            if (dsort::make_geom(key_type, values, mid, tu, t) == DSORT_OK && key(t) == k0)
+                a = mid;
+            else
+                b = mid - 1;
+        }
+        Geom e;
+        dsort::make_geom(key_type, values, a, tu, e);
+        if (e.total > ws) ws = e.total;
+        lo = a + 1;
+    }
+    return DSORT_OK;
+}
+
 extern "C" {
 
 int dsort_plan(dsort_plan_t *out, int key_type, int with_values, uint64_t max_items,
@@ -417,39 +471,15 @@ int dsort_plan(dsort_plan_t *out, int key_type, int with_values, uint64_t max_it
     if (max_segments > dsort::kMaxSegments) return DSORT_E_INVALID;
     dsort_tuning_t tu{};
     if (tuning) tu = *tuning;
-    // The workspace must serve every n <= max_items.  The geometry is piecewise in n: on each
-    // interval where (levels, rule, s1, s2, sample-sort and scan variants) stay fixed, every
-    // buffer grows with n, and these pieces never recur once left (the level count and the
-    // rule only grow with n, and so do s1 and s2 under one rule).  So the largest footprint is at the right end of some piece; walk the
-    // pieces, finding each right end by bisection.
+    // The workspace must serve every n <= max_items.
     size_t ws = 256;
-    if (max_items >= 2) {
-        auto key = [](const Geom &h) {
-            return ((uint64_t)(h.levels + 1) << 56) ^ ((uint64_t)h.plan_rule << 52) ^
-                   ((uint64_t)h.s1 << 36) ^ ((uint64_t)h.s2 << 12) ^
-                   ((uint64_t)h.samp_global << 1) ^ (uint64_t)h.scan_large;
-        };
-        uint64_t lo = 2;
-        while (lo <= max_items) {
-            Geom h;
-            if (dsort::make_geom(key_type, with_values != 0, lo, tu, h) != DSORT_OK)
-                return DSORT_E_UNSUPPORTED;
-            const uint64_t k0 = key(h);
-            uint64_t a = lo, b = max_items;
-            while (a < b) {
-                const uint64_t mid = a + (b - a + 1) / 2;
-                Geom t;
-                if (dsort::make_geom(key_type, with_values != 0, mid, tu, t) == DSORT_OK &&
-                    key(t) == k0)
-                    a = mid;
-                else
-                    b = mid - 1;
-            }
-            Geom e;
-            dsort::make_geom(key_type, with_values != 0, a, tu, e);
-            if (e.total > ws) ws = e.total;
-            lo = a + 1;
-        }
+    int rc = workspace_walk(key_type, with_values != 0, max_items, tu, ws);
+    if (rc != DSORT_OK) return rc;
+    if (tu.sampling) {
+        // a randomized call sorts its oversized buckets by further deterministic runs of the
+        // automatic plan, in the same workspace
+        rc = workspace_walk(key_type, with_values != 0, max_items, dsort_tuning_t{}, ws);
+        if (rc != DSORT_OK) return rc;
     }
     // Segmented calls: every buffer grows with n, S and the longest admissible segment; the
     // bound also covers every tuning the autotuner may choose.
@@ -526,6 +556,10 @@ int dsort_plan_geometry(dsort_plan_t plan, uint64_t n, dsort_geometry_t *out) {
     out->off_offsets = g->o_offs;
     out->off_buckets = g->o_buckets1;
     out->workspace_bytes = g->total;
+    out->sampling = g->random ? 1u : 0u;
+    out->bucket_limit = g->bucket_limit;
+    out->off_overflow_count = g->random ? g->o_status + 4ull * dsort::kOverflowWord : 0;
+    out->off_overflow_list = g->o_ovf;
     return DSORT_OK;
 }
 
@@ -653,6 +687,7 @@ int dsort_segmented(dsort_plan_t plan, void *d_keys, uint32_t *d_values, uint64_
                     const uint64_t *d_offsets, uint64_t num_segments, uint64_t max_segment,
                     void *d_workspace, void *stream) {
     if (!plan_ok(plan)) return DSORT_E_INVALID;
+    if (plan->tuning.sampling) return DSORT_E_UNSUPPORTED;  // randomized samples: plain sorts only
     if ((plan->values != 0) != (d_values != nullptr)) return DSORT_E_INVALID;
     if (n > plan->max_items || num_segments > plan->max_segments) return DSORT_E_INVALID;
     if (n == 0 || num_segments == 0) return DSORT_OK;

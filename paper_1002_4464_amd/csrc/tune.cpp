@@ -28,6 +28,7 @@ extern "C" int dsort_autotune_segmented(dsort_plan_t plan, const void *d_keys,
                                         void *stream, uint32_t repeats, dsort_seg_tuning_t *out) {
     using namespace dsort;
     if (!plan_valid(plan)) return DSORT_E_INVALID;
+    if (plan->tuning.sampling) return DSORT_E_UNSUPPORTED;  // randomized samples: plain sorts only
     const bool vals = plan->values != 0;
     if (vals != (d_values != nullptr) || vals != (d_scratch_values != nullptr))
         return DSORT_E_INVALID;

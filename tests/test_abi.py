@@ -265,3 +265,44 @@ def test_largest_plannable_sizes():
     for kt, v, limit in [(1, False, 1108377600), (3, False, 1108377600), (1, True, 554188800),
                          (2, False, 554188800), (2, True, 286326784)]:
         assert ok(kt, v, limit) and not ok(kt, v, limit + 1)
+
+
+def _random_tuning(**kw):
+    t = ds.Tuning(kw.get("L", 0), kw.get("s", 0), kw.get("L2", 0), kw.get("s2", 0),
+                  kw.get("levels", 0))
+    t.sampling = kw.get("sampling", 1)
+    t.seed = kw.get("seed", 1)
+    return t
+
+
+def test_random_sampling_plans_without_gpu():
+    """Randomized-sample plans: same level structure as the deterministic plan, a bucket limit
+    for the normal path (one workgroup at one level; the second level's capacity at two), a
+    workspace that also holds the deterministic plan's further runs, and refusal of segmented
+    calls and of unknown sampling modes."""
+    lib = ds.load_library()
+    for n, kt, vals in [(1_000_003, ds.U32, False), (1 << 24, ds.U32, False),
+                        (300_001, ds.U64, True), (1 << 26, ds.U32, True)]:
+        det = ds.Plan(kt, vals, n)
+        rnd = ds.Plan(kt, vals, n, _random_tuning(seed=5))
+        gd, gr = det.geometry(n), rnd.geometry(n)
+        assert (gr.levels, gr.sublist_len, gr.samples, gr.sublist_len2, gr.samples2) == \
+            (gd.levels, gd.sublist_len, gd.samples, gd.sublist_len2, gd.samples2)
+        assert gd.sampling == 0 and gd.bucket_limit == 0 and gr.sampling == 1
+        if gr.levels == 1:
+            assert gr.bucket_limit == gr.bucket_capacity
+        else:
+            # at least the deterministic bound, and a whole number of level-2 sublists
+            assert gr.bucket_limit >= gd.bucket_bound
+            assert gr.bucket_limit % gr.sublist_len2 == 0
+        assert gr.off_overflow_list > 0 and gr.off_overflow_count > gr.off_status
+        assert rnd.workspace_bytes >= det.workspace_bytes
+    h = ctypes.c_void_p()
+    wsb = ctypes.c_size_t()
+    bad = _random_tuning(sampling=2)
+    assert lib.dsort_plan(ctypes.byref(h), 1, 0, 1 << 20, 0, ctypes.byref(bad),
+                          ctypes.byref(wsb)) == ds.E_UNSUPPORTED
+    p = ds.Plan(ds.U32, False, 1 << 20, _random_tuning(), max_segments=16)
+    fake = ctypes.c_void_p(0x10000)
+    assert lib.dsort_segmented(p._h, fake, None, 1000, fake, 4, 0, ctypes.c_void_p(0x20000),
+                               None) == ds.E_UNSUPPORTED

@@ -11,12 +11,9 @@ import pytest
 
 import oracle
 import synth
-from helpers import from_dev, oracle_pool, samples_from_ws, say, to_dev, ws_view
+from helpers import check_level1, from_dev, gpu_sort, oracle_pool, say, to_dev, ws_view
 
 pytestmark = pytest.mark.gpu
-
-KT = {np.dtype(np.uint32): 1, np.dtype(np.uint64): 2, np.dtype(np.float32): 3}
-
 
 @pytest.fixture(scope="module")
 def ds(request):
@@ -74,47 +71,6 @@ def _start_heavy(d, selected):
 def _heavy(key):
     """The oracle result of one large configuration (released once taken)."""
     return _HEAVY.pop(key).result()
-
-
-def gpu_sort(ds, keys, values=None, tuning=None, plan=None):
-    import torch
-    kt = KT[keys.dtype]
-    if plan is None:
-        plan = ds.Plan(kt, values is not None, max(keys.size, 2), tuning)
-    tk = to_dev(keys)
-    ws = plan.workspace(tk.device)
-    if values is None:
-        plan.sort_keys(tk, ws)
-        tv = None
-    else:
-        tv = to_dev(values)
-        plan.sort_pairs(tk, tv, ws)
-    torch.cuda.synchronize()
-    geo = plan.geometry(keys.size)
-    status = int(ws_view(ws, geo.off_status, 1, np.uint32)[0])
-    assert status == 0, f"kernel status flags {status:#x}"
-    out_k = from_dev(tk, keys.dtype)
-    out_v = from_dev(tv, np.uint32) if tv is not None else None
-    return out_k, out_v, geo, ws
-
-
-def check_level1(geo, ws, tr, n):
-    """Level-1 intermediates equal the oracle's at the same (L, s)."""
-    m, s = geo.sublists, geo.samples
-    assert (m, s, geo.sublist_len) == (tr.m, tr.s, tr.L)
-    sk, sp = samples_from_ws(ws, geo.off_sorted_samples, m * s, geo.sample_bytes)
-    assert (sk == tr.sample_key).all(), "sorted sample keys (Step 4)"
-    assert (sp == tr.sample_pos).all(), "sorted sample positions (Step 4)"
-    counts = ws_view(ws, geo.off_counts, m * s, np.uint32).reshape(m, s)
-    assert (counts == tr.count).all(), "a_ij (Step 6)"
-    offs = ws_view(ws, geo.off_offsets, m * s, np.uint32).reshape(m, s)
-    assert (offs == tr.offset).all(), "l_ij (Step 7)"
-    b = ws_view(ws, geo.off_buckets, 4 * s, np.uint32).reshape(s, 4).astype(np.int64)
-    begin = tr.offset[0].astype(np.int64)
-    real = np.clip(n - begin, 0, tr.bucket_size.astype(np.int64))
-    assert (b[:, 0] == begin).all(), "bucket starts (Step 8)"
-    assert (b[:, 1] == real).all(), "bucket sizes (Step 8)"
-    assert (b[:, 2] == np.arange(s) * m).all() and (b[:, 3] == m).all(), "bucket piece ranges"
 
 
 # ------------------------------------------------------------------ small, one tile
