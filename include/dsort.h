@@ -105,6 +105,24 @@ int dsort_keys(dsort_plan_t plan, void *d_keys, uint64_t n, void *d_workspace, v
 int dsort_pairs(dsort_plan_t plan, void *d_keys, uint32_t *d_values, uint64_t n,
                 void *d_workspace, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same sort as dsort_keys (with_values = 0) or
+ * dsort_pairs (with_values = 1) under the automatic plan, with no plan and no caller workspace.
+ * The workspace is a fixed device array of DSORT_NOALLOC_SCRATCH_BYTES inside the library, one
+ * per GPU, created when the library's code is loaded on that GPU and held until the process
+ * ends; the call itself allocates nothing, host or device.  `n` is limited to sizes whose
+ * workspace (dsort_plan_geometry's workspace_bytes under the automatic plan) fits the array:
+ * 15,428,032 uint32/float32 keys, 8,083,264 32-bit keys with values, 7,944,672 uint64 keys
+ * and 5,131,264 uint64 keys with values.  Every call on one GPU shares that GPU's array, so calls
+ * that overlap on one GPU (two streams, two host threads) race and corrupt each other; calls
+ * must be ordered (one stream, or synchronised).  The array keeps the last call's
+ * intermediates; each call clears what it needs cleared on the device.
+ * Errors: DSORT_E_INVALID (bad type, pointers, alignment, or d_values given for with_values =
+ * 0), DSORT_E_CAPACITY (n above the limit; nothing is enqueued), DSORT_E_HIP. n <= 1: no-op. */
+#define DSORT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int dsort_sort_noalloc(int key_type, int with_values, void *d_keys, uint32_t *d_values,
+                       uint64_t n, void *stream);
+
 /* Release a plan (NULL is accepted). */
 int dsort_plan_destroy(dsort_plan_t plan);
 

@@ -13,10 +13,12 @@ from dataclasses import dataclass
 
 __all__ = [
     "U32", "U64", "F32", "DsortError", "Tuning", "Plan", "load_library", "sort", "sort_pairs",
-    "sort_segmented", "Server", "SegTuning", "strerror", "EXPORTED_SYMBOLS",
+    "sort_segmented", "sort_noalloc", "Server", "SegTuning", "strerror", "EXPORTED_SYMBOLS",
+    "NOALLOC_SCRATCH_BYTES",
 ]
 
 U32, U64, F32 = 1, 2, 3
+NOALLOC_SCRATCH_BYTES = 64 << 20  # DSORT_NOALLOC_SCRATCH_BYTES
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP, E_CAPACITY, E_TICKET = 0, -1, -2, -3, -4, -5, -6
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,7 +30,7 @@ EXPORTED_SYMBOLS = (
     "dsort_segmented", "dsort_segmented_geometry",
     "dsort_server_create", "dsort_submit", "dsort_poll", "dsort_release", "dsort_server_stats",
     "dsort_server_destroy", "dsort_set_seg_tuning", "dsort_get_seg_tuning",
-    "dsort_autotune_segmented",
+    "dsort_autotune_segmented", "dsort_sort_noalloc",
 )
 
 
@@ -169,6 +171,8 @@ def load_library(path: str = LIB_PATH):
     lib.dsort_server_stats.restype = I
     lib.dsort_server_destroy.argtypes = [P]
     lib.dsort_server_destroy.restype = I
+    lib.dsort_sort_noalloc.argtypes = [I, I, P, P, U64_, P]
+    lib.dsort_sort_noalloc.restype = I
     lib.dsort_last_error.argtypes = []
     lib.dsort_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -453,6 +457,28 @@ def sort_pairs(keys, values, key_type: int | None = None, stream=None):
     """Stable key/value sort in place; values are 4-byte elements."""
     kt = _key_type_of(keys, key_type)
     return _plan_for(kt, True, keys.numel()).sort_pairs(keys, values, stream=stream)
+
+
+def sort_noalloc(keys, values=None, key_type: int | None = None, stream=None):
+    """``sort`` (or ``sort_pairs`` with ``values``) through dsort_sort_noalloc: the library's
+    fixed per-GPU workspace, no plan, nothing allocated.  Calls on one GPU must not overlap."""
+    import torch
+    kt = _key_type_of(keys, key_type)
+    if not keys.is_cuda or (values is not None and not values.is_cuda):
+        raise ValueError("sort_noalloc needs device tensors")
+    if not keys.is_contiguous() or (values is not None and not values.is_contiguous()):
+        raise ValueError("sort_noalloc needs contiguous tensors")
+    if values is not None and values.numel() != keys.numel():
+        raise ValueError("keys and values differ in length")
+    if stream is None:
+        stream = torch.cuda.current_stream(keys.device)
+    with torch.cuda.device(keys.device):
+        rc = load_library().dsort_sort_noalloc(
+            kt, int(values is not None), ctypes.c_void_p(keys.data_ptr()),
+            ctypes.c_void_p(values.data_ptr()) if values is not None else None, keys.numel(),
+            ctypes.c_void_p(stream.cuda_stream))
+    _check(rc, "dsort_sort_noalloc")
+    return keys if values is None else (keys, values)
 
 
 def sort_segmented(keys, offsets, values=None, key_type: int | None = None, max_segment: int = 0,

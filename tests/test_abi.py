@@ -267,6 +267,31 @@ def test_largest_plannable_sizes():
         assert ok(kt, v, limit) and not ok(kt, v, limit + 1)
 
 
+NOALLOC_LIMITS = [(ds.U32, 0, 15_428_032), (ds.F32, 0, 15_428_032), (ds.U32, 1, 8_083_264),
+                  (ds.U64, 0, 7_944_672), (ds.U64, 1, 5_131_264)]
+
+
+@pytest.mark.parametrize("kt,values,limit", NOALLOC_LIMITS)
+def test_noalloc_limits_without_gpu(kt, values, limit):
+    """dsort_sort_noalloc serves n up to the stated limits (the automatic plan's workspace fits
+    the fixed array) and refuses one more item with DSORT_E_CAPACITY before touching the GPU;
+    bad arguments are refused the same way."""
+    lib = ds.load_library()
+    p = ds.Plan(kt, bool(values), limit + 1)
+    assert p.geometry(limit).workspace_bytes <= ds.NOALLOC_SCRATCH_BYTES
+    assert p.geometry(limit + 1).workspace_bytes > ds.NOALLOC_SCRATCH_BYTES
+    fake = ctypes.c_void_p(0x10000)
+    fv = fake if values else None
+    assert lib.dsort_sort_noalloc(kt, values, fake, fv, limit + 1, None) == ds.E_CAPACITY
+    assert lib.dsort_sort_noalloc(kt, values, None, fv, 1000, None) == ds.E_INVALID
+    assert lib.dsort_sort_noalloc(kt, values, ctypes.c_void_p(0x10002), fv, 1000,
+                                  None) == ds.E_INVALID
+    assert lib.dsort_sort_noalloc(kt, 1, fake, None, 1000, None) == ds.E_INVALID
+    assert lib.dsort_sort_noalloc(kt, 0, fake, fake, 1000, None) == ds.E_INVALID
+    assert lib.dsort_sort_noalloc(7, values, fake, fv, 1000, None) == ds.E_INVALID
+    assert lib.dsort_sort_noalloc(kt, values, None, None, 1, None) == ds.OK
+
+
 def _random_tuning(**kw):
     t = ds.Tuning(kw.get("L", 0), kw.get("s", 0), kw.get("L2", 0), kw.get("s2", 0),
                   kw.get("levels", 0))
