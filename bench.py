@@ -64,7 +64,8 @@ STAGE_GROUPS = {
 def group_bytes(group: str, n: int, g, kb: int) -> float:
     """Algorithmic HBM bytes one step of a stage group must move:
     a sort or move of the data reads and writes n keys once; ranking reads the sorted sublists
-    once plus the splitters and writes the counts; samples, counts and offsets are small."""
+    once plus the splitters and writes the counts; the scan reads the m x s counts twice (column
+    sums, then the update) and writes the offsets, piece destinations and piece sources."""
     sb = g.sample_bytes
     m1s1 = g.sublists * g.samples
     m2s2 = -(-n // max(g.sublist_len2, 1)) * g.samples2 if g.levels == 2 else 0
@@ -72,8 +73,11 @@ def group_bytes(group: str, n: int, g, kb: int) -> float:
         "steps1-3 local sort + sampling": 2 * n * kb + m1s1 * sb,
         "step4 sample sort": 2 * m1s1 * sb,
         "steps5-6 rank": n * kb + m1s1 * (sb + 4),
+        "step7 scan": 5 * m1s1 * 4,
         "step8 + level2 steps1-3": 2 * n * kb + 2 * m1s1 * 4 + m2s2 * sb,
+        "level2 step4": 2 * m2s2 * sb,
         "level2 steps5-6": n * kb + m2s2 * (sb + 4),
+        "level2 step7": 5 * m2s2 * 4,
         "steps8-9 gather + bucket sort": 2 * n * kb,
     }.get(group, 0.0)
 

@@ -237,7 +237,7 @@ int dsort_segmented_geometry(dsort_plan_t plan, uint64_t n, uint64_t num_segment
  * the speed. */
 typedef struct {
     uint32_t classes;
-    uint32_t reserved;
+    uint32_t from_cache;   /* set by dsort_autotune_segmented: 1 = read from its cache file */
     uint64_t upper[4];
     uint32_t sublist_len[4];
     uint32_t samples[4];
@@ -262,7 +262,13 @@ int dsort_get_seg_tuning(dsort_plan_t plan, dsort_seg_tuning_t *out);
  * buffers (n keys, and n values for key/value plans) and sorts there, `repeats` times (at least
  * 1), timed with HIP events on `stream`.  Blocks until done.  Arguments as for dsort_segmented.
  * On success *out (may be NULL) receives the tuning; when the defaults win they are installed
- * as an explicit tuning with their (L, s) per class (no classes when no segment is long). */
+ * as an explicit tuning with their (L, s) per class (no classes when no segment is long).
+ * Persistence: if the environment variable DSORT_TUNE_CACHE names a file, a result is stored
+ * there under (device: architecture, name and CU count; key type; values or not; segment class
+ * = ceil(log2(max_segment))), and a later call with the same key installs the stored tuning
+ * without timing anything (out->from_cache = 1) as long as it fits the plan.  The file is plain
+ * text, rewritten through a temporary file and a rename; a write that fails only loses the
+ * entry. */
 int dsort_autotune_segmented(dsort_plan_t plan, const void *d_keys, const uint32_t *d_values,
                              uint64_t n, const uint64_t *d_offsets, uint64_t num_segments,
                              uint64_t max_segment, void *d_scratch_keys,

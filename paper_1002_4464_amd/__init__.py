@@ -80,7 +80,7 @@ class _SegGeometry(ctypes.Structure):
 class SegTuning(ctypes.Structure):
     """Long-segment classes of segmented sorts: class c holds lengths in (upper[c-1], upper[c]]
     with sublist length sublist_len[c] and samples[c] (0 = defaults); classes = 0: defaults."""
-    _fields_ = [("classes", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+    _fields_ = [("classes", ctypes.c_uint32), ("from_cache", ctypes.c_uint32),
                 ("upper", ctypes.c_uint64 * 4), ("sublist_len", ctypes.c_uint32 * 4),
                 ("samples", ctypes.c_uint32 * 4)]
 

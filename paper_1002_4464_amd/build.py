@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdsort.so")
-SOURCES = ["kernels.hip", "noalloc.hip", "plan.cpp", "server.cpp", "tune.cpp"]
+SOURCES = ["kernels.hip", "noalloc.hip", "plan.cpp", "server.cpp", "tune.cpp", "tune_cache.cpp"]
 ARCH = "gfx950"
 
 

@@ -5,6 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
 #include <vector>
 
 #include "../../include/dsort.h"
@@ -165,6 +166,18 @@ void set_last_error(const char *stage, const char *name, const char *text);
 constexpr uint64_t kMaxItems = (1ull << 32) - (1ull << 16);
 
 int plan_set_seg_tuning(dsort_plan_s *plan, const SegTuning &tu);
+
+// Persisted autotuner results (tune_cache.cpp): one tuning per (device, key type, values,
+// segment class = ceil(log2(max_segment))) in a text file.
+struct TuneKey {
+    std::string device;  // architecture, marketing name and CU count
+    int key_type = 0;
+    bool values = false;
+    uint32_t seg_class = 0;
+};
+uint32_t tune_seg_class(uint64_t max_segment);
+bool tune_cache_lookup(const char *path, const TuneKey &key, SegTuning &out);
+bool tune_cache_store(const char *path, const TuneKey &key, const SegTuning &t);
 
 }  // namespace dsort
 

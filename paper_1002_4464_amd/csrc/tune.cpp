@@ -1,6 +1,8 @@
 // Autotuner of the segmented sort: per length class of the long segments, the sublist length L
 // and the samples per sublist s that sort the caller's batch fastest, measured with HIP events.
 #include <hip/hip_runtime_api.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -17,6 +19,33 @@ struct Events {
         if (b) (void)hipEventDestroy(b);
     }
 };
+
+// The current device as the tuning cache names it: architecture, marketing name, CU count.
+bool device_id(std::string &out) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    char buf[512];
+    snprintf(buf, sizeof(buf), "%s/%s/%dcu", prop.gcnArchName, prop.name,
+             prop.multiProcessorCount);
+    out = buf;
+    return true;
+}
+
+void tuning_out(const dsort::SegTuning &t, bool from_cache, dsort_seg_tuning_t *out) {
+    if (!out) return;
+    memset(out, 0, sizeof(*out));
+    out->classes = t.classes;
+    out->from_cache = from_cache ? 1u : 0u;
+    for (int q = 0; q < dsort::kMaxSegClasses; ++q) {
+        out->upper[q] = t.upper[q];
+        out->sublist_len[q] = t.L[q];
+        out->samples[q] = t.s[q];
+    }
+}
 
 }  // namespace
 
@@ -47,6 +76,23 @@ extern "C" int dsort_autotune_segmented(dsort_plan_t plan, const void *d_keys,
     SegGeom g0;
     int rc = make_seg_geom(plan->key_type, vals, n, num_segments, max_segment, SegTuning{}, g0);
     if (rc != DSORT_OK) return rc;
+    // A result persisted for this device, layout and segment class (DSORT_TUNE_CACHE names the
+    // file) is installed without timing, if it still fits this plan.
+    const char *cache = getenv("DSORT_TUNE_CACHE");
+    if (cache && !*cache) cache = nullptr;
+    TuneKey key;
+    key.key_type = plan->key_type;
+    key.values = vals;
+    key.seg_class = tune_seg_class(g0.max_seg);
+    if (cache && !device_id(key.device)) cache = nullptr;
+    if (cache) {
+        SegTuning cached;
+        if (tune_cache_lookup(cache, key, cached) &&
+            plan_set_seg_tuning(plan, cached) == DSORT_OK) {
+            tuning_out(cached, true, out);
+            return DSORT_OK;
+        }
+    }
     SegTuning best = seg_default_split(plan->key_type, vals, g0.max_seg);
     uint32_t Ls[4];
     const int nL = seg_candidate_L(c, Ls);
@@ -176,14 +222,7 @@ extern "C" int dsort_autotune_segmented(dsort_plan_t plan, const void *d_keys,
     }
     rc = plan_set_seg_tuning(plan, best);
     if (rc != DSORT_OK) return rc;
-    if (out) {
-        memset(out, 0, sizeof(*out));
-        out->classes = best.classes;
-        for (int q = 0; q < kMaxSegClasses; ++q) {
-            out->upper[q] = best.upper[q];
-            out->sublist_len[q] = best.L[q];
-            out->samples[q] = best.s[q];
-        }
-    }
+    if (cache) (void)tune_cache_store(cache, key, best);  // a failed write only loses the cache
+    tuning_out(best, false, out);
     return DSORT_OK;
 }

@@ -324,6 +324,41 @@ def test_autotune_installs_and_keeps_input(ds):
     assert (out == want).all()
 
 
+def test_autotune_cache_file(ds, tmp_path, monkeypatch):
+    """With DSORT_TUNE_CACHE set, a tuning is stored under (device, layout, segment class); a
+    second autotune call for another batch of the same class installs it without timing and
+    sorts under it still give the oracle's result."""
+    import torch
+    path = tmp_path / "dsort_tune.txt"
+    monkeypatch.setenv("DSORT_TUNE_CACHE", str(path))
+    sizes = synth.segment_sizes(150, 62, 8, 19)
+    offs, n = offsets_of(sizes)
+    keys = synth.uniform_u32(n, 62)
+    plan = ds.Plan(1, False, n, max_segments=sizes.size)
+    t1 = plan.autotune_segmented(to_dev(keys), torch.from_numpy(offs).cuda(),
+                                 max_segment=int(sizes.max()), repeats=1)
+    torch.cuda.synchronize()
+    assert t1.from_cache == 0
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("v1 ")
+    # another batch of the same longest-segment class, on a new plan
+    sizes2 = synth.segment_sizes(150, 63, 8, 19)
+    sizes2[0] = int(sizes.max())
+    offs2, n2 = offsets_of(sizes2)
+    keys2 = synth.normal_f32_segments(sizes2, 64).view(np.uint32)
+    plan2 = ds.Plan(1, False, max(n, n2), max_segments=sizes2.size)
+    t2 = plan2.autotune_segmented(to_dev(keys2), torch.from_numpy(offs2).cuda(),
+                                  max_segment=int(sizes2.max()), repeats=1)
+    torch.cuda.synchronize()
+    say("[seg] cached tuning", t2.as_dict())
+    assert t2.from_cache == 1 and t2.as_dict() == t1.as_dict()
+    assert plan2.seg_tuning().as_dict() == t1.as_dict()
+    assert len(path.read_text().splitlines()) == 1
+    out, _, _ = gpu_segmented(ds, keys2, offs2, plan=plan2, max_segment=int(sizes2.max()))
+    want, _ = oracle.segmented_sort(keys2, offs2)
+    assert (out == want).all()
+
+
 def test_concurrent_calls_from_two_threads(ds):
     """Segmented calls from two host threads, each on its own plan and stream, at the same
     time: the bucket size classes of both share the library's side streams, and every result

@@ -1,8 +1,9 @@
-"""Host-only builds of the oracle (oracle/dss_oracle.c) and of the planner (csrc/plan.cpp, the
-HIP pipeline replaced by stubs), plainly and under AddressSanitizer/UBSan, each driven over many
-random inputs by a small checker in tests/cpp (oracle: output against its stable sort and the
-trace's bookkeeping; planner: every geometry inside the plan's workspace, regions disjoint,
-Section 4's bound for the chosen (L, s))."""
+"""Host-only builds of the oracle (oracle/dss_oracle.c), of the planner (csrc/plan.cpp, the HIP
+pipeline replaced by stubs) and of the autotuner's result file (csrc/tune_cache.cpp), plainly and
+under AddressSanitizer/UBSan, each driven by a small checker in tests/cpp (oracle: output against
+its stable sort and the trace's bookkeeping over many random inputs; planner: every geometry
+inside the plan's workspace, regions disjoint, Section 4's bound for the chosen (L, s); tuning
+file: round trips and replacement by key)."""
 import os
 import shutil
 import subprocess
@@ -15,9 +16,9 @@ FLAGS = {"plain": [], "asan-ubsan": ["-fsanitize=address,undefined",
                                      "-fno-sanitize-recover=undefined"]}
 
 
-def _run(exe):
+def _run(exe, *args):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="halt_on_error=1")
-    r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
+    r = subprocess.run([exe, *args], capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "ALL OK" in r.stdout
     assert "runtime error" not in r.stderr, r.stderr
@@ -46,3 +47,17 @@ def test_planner_sanitized(tmp_path, mode):
                            os.path.join(ROOT, "paper_1002_4464_amd", "csrc", "plan.cpp"),
                            "-o", exe])
     _run(exe)
+
+
+@pytest.mark.parametrize("mode", sorted(FLAGS))
+def test_tune_cache_sanitized(tmp_path, mode):
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path / "tune_cache_test")
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-g", "-Wall", *FLAGS[mode],
+                           "-I", os.path.join(ROOT, "include"),
+                           "-I", os.path.join(ROOT, "paper_1002_4464_amd", "csrc"),
+                           os.path.join(CPP, "tune_cache_test.cpp"),
+                           os.path.join(ROOT, "paper_1002_4464_amd", "csrc", "tune_cache.cpp"),
+                           "-o", exe])
+    _run(exe, str(tmp_path))
