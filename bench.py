@@ -38,7 +38,9 @@ HBM_PEAK_GBS = 8000.0
 # taking four clocks per wave instruction), 256 CUs at 2.4 GHz.
 VALU_PEAK_G = 256 * 2.4
 METRIC = "Mkeys/s + HBM GB/s (2^28 u32); p50/p99 latency, batched/served vs plain sort"
-KERNEL_SRC = os.path.join(ROOT, "paper_1002_4464_amd", "csrc", "kernels.hip")
+# device sources whose hash keys the recorded counter files (profiles/*.json)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1002_4464_amd", "csrc", f)
+               for f in ("kernels.hip", "steps.h", "sort_primitives.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "valu.json")
 
@@ -83,8 +85,11 @@ def group_bytes(group: str, n: int, g, kb: int) -> float:
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_for(stage: str):
