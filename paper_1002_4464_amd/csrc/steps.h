@@ -90,17 +90,18 @@ __device__ __forceinline__ void tile_gather(const uint32_t *pdst, const uint32_t
             }
             p = l;
         }
-        for (uint32_t row = xs; row < xe; row += 4 * wl) {
-            uint32_t si[4];
+        // eight rows of the wave's share per pass: their loads are in flight together
+        for (uint32_t row = xs; row < xe; row += 8 * wl) {
+            uint32_t si[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 8; ++u) {
                 const uint32_t xu = row + wl * u + lane;
                 if (xu < xe) {
                     while (xu >= tb[p + 1]) ++p;
                     si[u] = sb[p] + xu;
                 }
             }
-            store.template run<4>(row + lane, wl, xe, si);
+            store.template run<8>(row + lane, wl, xe, si);
         }
     }
 }
@@ -203,16 +204,21 @@ __global__ __launch_bounds__(CAP / E) void k_tile(TileArgs a) {
                     p_first, p_last, tb, sb, GatherKeys<K, R, T>{src, lds, a.sv.n_total});
         for (uint32_t i = count + tid; i < P; i += bd) lds[pidx<T>(i)] = R::pad(i);
     } else {
-        for (uint32_t i = tid; i < P; i += bd) {
-            T e;
-            if (i < count) {
-                K k = src[begin + i];
+        // P <= E * blockDim.x: every thread's E loads are issued before any is waited for
+        K v[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const uint32_t i = tid + q * bd;
+            v[q] = i < count ? src[begin + i] : KeyMax<K>::v;
+        }
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const uint32_t i = tid + q * bd;
+            if (i < P) {
+                K k = v[q];
                 if (XIN) k = (K)f32_in((uint32_t)k);
-                e = R::make(k, i);
-            } else {
-                e = R::pad(i);
+                lds[pidx<T>(i)] = i < count ? R::make(k, i) : R::pad(i);
             }
-            lds[pidx<T>(i)] = e;
         }
     }
     __syncthreads();
@@ -263,7 +269,19 @@ __global__ __launch_bounds__(CAP / E) void k_tile(TileArgs a) {
                         count, p_first, p_last, tb, sb,
                         GatherVals<T>{a.src_vals, lds, a.sv.n_total});
         else
-            for (uint32_t i = tid; i < count; i += bd) put_val<T>(lds, i, a.src_vals[begin + i]);
+        {
+            uint32_t vv[E];
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                const uint32_t i = tid + q * bd;
+                vv[q] = i < count ? a.src_vals[begin + i] : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                const uint32_t i = tid + q * bd;
+                if (i < count) put_val<T>(lds, i, vv[q]);
+            }
+        }
         __syncthreads();
 #pragma unroll 2
         for (int q = 0; q < E; ++q) {
@@ -306,8 +324,19 @@ __global__ __launch_bounds__(CAP / E) void k_sort_samples(const SC *src, SC *dst
         return;
     }
     const uint32_t P = max((uint32_t)E, pow2_at_least(count));
-    for (uint32_t i = tid; i < P; i += blockDim.x)
-        lds[pidx<SC>(i)] = i < count ? src[begin + i] : MaxOf<SC>::get();
+    {  // P <= E * blockDim.x: all of a thread's loads in flight together
+        SC v[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const uint32_t i = tid + q * blockDim.x;
+            v[q] = i < count ? src[begin + i] : MaxOf<SC>::get();
+        }
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const uint32_t i = tid + q * blockDim.x;
+            if (i < P) lds[pidx<SC>(i)] = v[q];
+        }
+    }
     __syncthreads();
     // Each sublist's s samples are already in order (they come from its sorted items) and
     // every range starts on a row, so the sort starts from runs of s; sample composites are

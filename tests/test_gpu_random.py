@@ -78,6 +78,18 @@ def test_random_two_levels_2p24(ds, dist):
     assert geo.levels == 2
 
 
+@pytest.mark.parametrize("dist", sorted(synth.DISTRIBUTIONS_U32))
+def test_random_2p26_benchmark_plan(ds, dist):
+    """The randomized runs the benchmark times: 2^26 uint32 keys of each distribution (seeds
+    2-7), automatic plan, seed 2024; output and level-1 intermediates against the oracle."""
+    n = 1 << 26
+    seeds = {"uniform": 2, "gaussian": 3, "bucket": 4, "staggered": 5, "sorted": 6, "equal": 7}
+    say(f"random 2^26 {dist}")
+    geo, _ = run_and_check(ds, synth.make_u32(dist, n, seeds[dist]), None,
+                           rnd_tuning(ds, 2024), 2024)
+    assert geo.levels == 2
+
+
 @pytest.mark.parametrize("kind", ["u32_pairs", "u64", "u64_pairs", "f32"])
 def test_random_types(ds, kind):
     n = 300_001
