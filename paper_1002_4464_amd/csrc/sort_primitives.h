@@ -546,6 +546,80 @@ __device__ __forceinline__ void serial_merge(const T *lds, uint32_t ai, uint32_t
     }
 }
 
+// Merges of 32-bit keys (no positions) on a bitonic layout: in every run pair the first run
+// A is stored ascending and the second run B descending, so that reading past the end of
+// either run reads the other run's largest items instead of unrelated ones.  A thread that
+// has used up A then sees B's maximum: it takes B's items until the one it reads from B's
+// end equals the B item it holds, and then every item left is that maximum, so the values it
+// outputs are right whichever side it takes them from.  A thread that has used up B sees A's
+// maximum and takes A, as it must.  So the serial merge needs no bounds tests.  The pointers of
+// one thread never cross, because it outputs no more items than the pair has left, so every
+// read stays in [base, base + na + nb] (the element one past the pair is read, unused, when a
+// thread's outputs end at the pair's end).
+
+// Merge-path split of the first `diag` outputs of A = lds[base, base + na) (ascending) and B
+// (nb items, descending from base + na + nb - 1): the largest a whose A[a - 1] does not follow
+// B[diag - a], by the same clamped halving steps as merge_split.
+__device__ __forceinline__ uint32_t merge_split_bit(const uint32_t *lds, uint32_t base,
+                                                    uint32_t na, uint32_t nb, uint32_t diag,
+                                                    uint32_t top) {
+    const uint32_t lo = diag > nb ? diag - nb : 0, hi = min(diag, na);
+    uint32_t pos = lo;
+    if (lo < hi) {
+        const uint32_t am1 = base - 1, br = base + na + nb - 1 - diag;  // A[q-1], B[diag-q]
+        for (uint32_t step = top; step; step >>= 1) {
+            const uint32_t q = min(pos + step, hi);
+            const uint32_t av = lds_at<uint32_t>(lds, am1 + q);
+            const uint32_t bv = lds_at<uint32_t>(lds, br + q);
+            pos = bv < av ? pos : q;
+        }
+    }
+    return pos;
+}
+
+// Serial merge of E outputs on the bitonic layout: pa walks A upwards, pb walks B downwards
+// (B's next item is at pb); A wins ties.  pa and pb are left at the next unmerged items.
+template <int E>
+__device__ __forceinline__ void serial_merge_bit(const uint32_t *lds, uint32_t &pa, uint32_t &pb,
+                                                 uint32_t (&out)[E]) {
+    uint32_t av = lds_at<uint32_t>(lds, pa);
+    uint32_t bv = lds_at<uint32_t>(lds, pb);
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const bool take_a = !(bv < av);
+        out[k] = take_a ? av : bv;
+        pa += take_a ? 1u : 0u;
+        pb -= take_a ? 0u : 1u;
+        const uint32_t v = lds_at<uint32_t>(lds, take_a ? pa : pb);
+        av = take_a ? v : av;
+        bv = take_a ? bv : v;
+    }
+}
+
+// Stores E registers into the block lds[blk, blk + E) (blk a multiple of E; padded indexing),
+// in order or reversed.  When E is a power of two within one padding period the block never
+// straddles a pad, so each store is one immediate offset from a common address.
+template <class T, int E>
+__device__ __forceinline__ void store_block(T *lds, uint32_t blk, bool rev, const T (&x)[E]) {
+    if constexpr ((E & (E - 1)) == 0 && E <= (1 << PadShift<T>::v)) {
+        blk &= ~(uint32_t)(E - 1);
+        T *p = lds + pidx<T>(blk);
+        if (rev) {
+#pragma unroll
+            for (int k = 0; k < E; ++k) p[E - 1 - k] = x[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < E; ++k) p[k] = x[k];
+        }
+    } else if (rev) {
+#pragma unroll
+        for (int k = 0; k < E; ++k) lds[pidx<T>(blk + E - 1 - k)] = x[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < E; ++k) lds[pidx<T>(blk + k)] = x[k];
+    }
+}
+
 // Sorts lds[0, P) in place (P a multiple of E, E <= P <= E * blockDim.x; lds must hold
 // lds_elems(P) + 1 elements, the last one only ever read speculatively).  Thread t owns
 // items [tE, tE+E): a register network sorts them, then merge passes double the sorted run
@@ -556,6 +630,8 @@ __device__ __forceinline__ void serial_merge(const T *lds, uint32_t ai, uint32_t
 // the sixth, across whole waves, when it is one of 1024 (dpp_merge_1024).  R0 > E: lds already
 // holds sorted runs of R0 items (R0 a power of two times E), so sorting starts with the
 // merge pass of those runs.
+// Keys-only 32-bit sorts with E = 16 merge on the bitonic layout (see merge_split_bit), so
+// their serial merges carry no bounds tests.
 // All threads of the block must call it.  COMP: see MergeLess (the register network always
 // compares whole elements; only the merges may compare keys alone).  TWO: when P is a multiple
 // of 2E, every LDS merge pass gives each active thread two consecutive blocks of E outputs, so
@@ -570,6 +646,16 @@ __device__ __forceinline__ void block_sort(T *lds, uint32_t P, uint32_t R0 = E) 
     const bool dpp16 = dpp && P % 256 == 0;  // whole 16-lane rows: one more register merge
     const bool dpp32 = dpp && P % 512 == 0;  // whole 32-lane halves: and another
     const bool dpp64 = dpp && P % 1024 == 0;  // whole waves: and one more
+    const uint32_t Rs = R0 > E         ? R0
+                        : dpp64   ? 64 * E
+                        : dpp32   ? 32 * E
+                        : dpp16   ? 16 * E
+                        : dpp     ? 8 * E
+                                  : E;
+    // keys-only 32-bit merges with 16 items per thread run on the bitonic layout (odd runs
+    // stored descending; with 20 or 32 items per thread it raised the bucket kernels' VGPRs
+    // from 69 to 85 and more and lost there)
+    constexpr bool BIT = sizeof(T) == 4 && !COMP && E == 16;
     T x[E];
     if (R0 <= E && act) {
 #pragma unroll
@@ -581,15 +667,50 @@ __device__ __forceinline__ void block_sort(T *lds, uint32_t P, uint32_t R0 = E) 
             if (dpp32) dpp_merge_512(x);
             if (dpp64) dpp_merge_1024(x);
         }
+        const uint32_t run = t * E / Rs;  // P is a multiple of Rs: every run is full
+        if (BIT && Rs < P) {
+            const bool rev = run & 1;  // odd runs descending: block t goes to its mirror
+            store_block<T, E>(lds, rev ? 2 * run * Rs + Rs - E - t * E : t * E, rev, x);
+        } else {
 #pragma unroll
-        for (int k = 0; k < E; ++k) lds[pidx<T>(t * E + k)] = x[k];
+            for (int k = 0; k < E; ++k) lds[pidx<T>(t * E + k)] = x[k];
+        }
     }
-    const uint32_t Rs = R0 > E         ? R0
-                        : dpp64   ? 64 * E
-                        : dpp32   ? 32 * E
-                        : dpp16   ? 16 * E
-                        : dpp     ? 8 * E
-                                  : E;
+    if constexpr (BIT) {
+        const bool two = TWO && P % (2 * E) == 0;
+        const uint32_t EB = two ? 2 * E : E;  // outputs per active thread
+        const bool actb = t * EB < P;
+        for (uint32_t R = Rs, pair = 2 * Rs / E, top = pow2_at_least(Rs); R < P;
+             R <<= 1, pair <<= 1, top <<= 1) {
+            __syncthreads();
+            // a pair holds 2R items: pair threads of E outputs (pair / 2 of 2E outputs)
+            const uint32_t tp = two ? pair / 2 : pair;
+            const uint32_t base = (t & ~(tp - 1)) * EB;  // first item of the thread's run pair
+            const uint32_t diag = t * EB - base;
+            const uint32_t na = min(R, P - base);
+            const uint32_t nb = min(R, P - base - na);
+            T y[E];
+            if (actb) {
+                const uint32_t a = merge_split_bit(lds, base, na, nb, diag, top);
+                uint32_t pa = base + a, pb = base + na + nb - 1 - (diag - a);
+                serial_merge_bit<E>(lds, pa, pb, x);
+                if (two) serial_merge_bit<E>(lds, pa, pb, y);
+            }
+            __syncthreads();
+            if (actb) {
+                // the merged run is the next pass's A (ascending) or B (descending); the last
+                // pass leaves everything ascending
+                const bool desc = 2 * R < P && (t & tp);  // odd pair: B of the next pass
+                // na, nb, diag are multiples of E: output block q of the thread lands on an
+                // E-aligned block, at its mirror image in the pair when descending
+                const uint32_t mir = base + na + nb - E - diag;
+                store_block<T, E>(lds, desc ? mir : base + diag, desc, x);
+                if (two) store_block<T, E>(lds, desc ? mir - E : base + diag + E, desc, y);
+            }
+        }
+        __syncthreads();
+        return;
+    }
     for (uint32_t R = Rs, pair = 2 * Rs / E, top = pow2_at_least(Rs); R < P;
          R <<= 1, pair <<= 1, top <<= 1) {
         __syncthreads();

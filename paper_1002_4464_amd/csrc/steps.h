@@ -156,8 +156,13 @@ template <class T> struct GatherVals {
 // items, sorted from src into dst (which may alias).  XIN/XOUT apply the f32 order map.
 // GIN (MODE_SAMPLE, second level): the sublist is gathered from the previous level's pieces
 // (see tile_gather) and the sorted sublist goes to dst, which must not alias src.
+// Keys-only 32-bit tiles of 1024 threads ask for eight waves per SIMD (at most 64 VGPRs), which
+// two resident workgroups per CU need.
+template <class K, bool V, int E, int CAP>
+constexpr int tile_waves_per_eu() { return !V && sizeof(K) == 4 && CAP / E == 1024 ? 8 : 1; }
+
 template <class K, bool V, int E, int CAP, int MODE, bool XIN, bool XOUT, bool GIN = false>
-__global__ __launch_bounds__(CAP / E) void k_tile(TileArgs a) {
+__global__ __launch_bounds__(CAP / E, (tile_waves_per_eu<K, V, E, CAP>())) void k_tile(TileArgs a) {
     using R = Tr<K, V>;
     using T = typename R::T;
     static_assert(!GIN || (MODE == MODE_SAMPLE && !XIN), "piece gathers feed Steps 1-3 only");
