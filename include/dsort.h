@@ -45,9 +45,11 @@ enum {
 };
 
 /* Optional tuning.  Zero in a field means "choose automatically".
- *  sublist_len  L  of the first level (Step 1: the sublist length n/m), power of two;
+ *  sublist_len  L  of the first level (Step 1: the sublist length n/m): a power of two, or
+ *                  a multiple of 1024 (512 for 64-bit keys with values), at most 16384 (8192
+ *                  for 64-bit keys with values);
  *  samples      s  of the first level (Step 3: samples per sublist = number of buckets),
- *                  power of two dividing L;
+ *                  at most 1024, dividing L;
  *  sublist_len2, samples2: the same for the second level (Step 9 run as a segmented sort);
  *  levels       0 = auto, 1 = force one level (Step 9 sorts each bucket in one workgroup),
  *               2 = force two levels;

@@ -34,6 +34,13 @@ constexpr uint64_t kMaxSamples = 1024;  // per-sublist tables live in LDS
 constexpr uint64_t kMaxPieces = 256;    // pieces per bucket the fused Steps 8-9 accept
 constexpr uint64_t kNumClasses = 8;     // size classes of the fused Steps 8-9
 
+// A level's sublist length: a power of two, or a multiple of 64 items per thread (the tile
+// kernel then runs whole waves); its sample count divides it (Step 3's chunks of L/s items).
+bool level_L_ok(const Caps &c, uint64_t L) {
+    return L >= c.tile_e && L <= c.tile_max && (is_pow2(L) || L % (64 * (uint64_t)c.tile_e) == 0);
+}
+bool level_s_ok(uint64_t s, uint64_t L) { return s && s <= L && s <= kMaxSamples && L % s == 0; }
+
 }  // namespace
 
 Caps caps_for(int key_type, bool values) {
@@ -89,9 +96,8 @@ int make_geom(int key_type, bool values, uint64_t n, const dsort_tuning_t &tu, G
     }
 
     const uint64_t L1 = tu.sublist_len ? tu.sublist_len : c.tile_max;
-    if (!is_pow2(L1) || L1 < c.tile_e || L1 > c.tile_max) return DSORT_E_UNSUPPORTED;
-    if (tu.samples && (!is_pow2(tu.samples) || tu.samples > L1 || tu.samples > kMaxSamples))
-        return DSORT_E_UNSUPPORTED;
+    if (!level_L_ok(c, L1)) return DSORT_E_UNSUPPORTED;
+    if (tu.samples && !level_s_ok(tu.samples, L1)) return DSORT_E_UNSUPPORTED;
     const uint64_t m1 = ceil_div(n, L1);
     if (m1 * L1 > kMaxItems + L1) return DSORT_E_UNSUPPORTED;
 
@@ -118,9 +124,8 @@ int make_geom(int key_type, bool values, uint64_t n, const dsort_tuning_t &tu, G
         // --- two levels: the smallest s1 for which every bucket can be sorted by one more
         // level whose samples fit one workgroup (Step 4 of the second level stays local).
         L2 = tu.sublist_len2 ? tu.sublist_len2 : c.tile_max;
-        if (!is_pow2(L2) || L2 < c.tile_e || L2 > c.tile_max) return DSORT_E_UNSUPPORTED;
-        if (tu.samples2 && (!is_pow2(tu.samples2) || tu.samples2 > L2 || tu.samples2 > kMaxSamples))
-            return DSORT_E_UNSUPPORTED;
+        if (!level_L_ok(c, L2)) return DSORT_E_UNSUPPORTED;
+        if (tu.samples2 && !level_s_ok(tu.samples2, L2)) return DSORT_E_UNSUPPORTED;
         // Untuned choices prefer (measured at 2^25 to 2^28, 32-bit keys with and without values:
         // up to 5 % faster than the smallest feasible s1 and s2) s1 >= n / 2^19, capped at 256
         // (about 32 level-2 sublists per level-1 bucket; more samples, e.g. s1 = 512 at 2^28,

@@ -586,13 +586,20 @@ __device__ __forceinline__ void serial_merge_bit(const uint32_t *lds, uint32_t &
     uint32_t bv = lds_at<uint32_t>(lds, pb);
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-        const bool take_a = !(bv < av);
-        out[k] = take_a ? av : bv;
-        pa += take_a ? 1u : 0u;
-        pb -= take_a ? 0u : 1u;
-        const uint32_t v = lds_at<uint32_t>(lds, take_a ? pa : pb);
-        av = take_a ? v : av;
-        bv = take_a ? bv : v;
+        const uint32_t ta = bv >= av ? 1u : 0u;
+        // keys alone: the output is the smaller head, whichever side it comes from; pinned
+        // here (an empty asm) so that the compiler does not keep both heads of every step
+        // alive until the stores
+        out[k] = min(av, bv);
+        asm volatile("" : "+v"(out[k]));
+        pa += ta;
+        pb = pb + ta - 1u;
+        // both pointers as plain registers: left alone, the compiler re-derives them from
+        // running sums of the take flags, one more compare and select per step
+        asm("" : "+v"(pa), "+v"(pb));
+        const uint32_t v = lds_at<uint32_t>(lds, ta ? pa : pb);
+        av = ta ? v : av;
+        bv = ta ? bv : v;
     }
 }
 
@@ -630,8 +637,8 @@ __device__ __forceinline__ void store_block(T *lds, uint32_t blk, bool rev, cons
 // the sixth, across whole waves, when it is one of 1024 (dpp_merge_1024).  R0 > E: lds already
 // holds sorted runs of R0 items (R0 a power of two times E), so sorting starts with the
 // merge pass of those runs.
-// Keys-only 32-bit sorts with E = 16 merge on the bitonic layout (see merge_split_bit), so
-// their serial merges carry no bounds tests.
+// Keys-only 32-bit sorts merge on the bitonic layout (see merge_split_bit), so their serial
+// merges carry no bounds tests.
 // All threads of the block must call it.  COMP: see MergeLess (the register network always
 // compares whole elements; only the merges may compare keys alone).  TWO: when P is a multiple
 // of 2E, every LDS merge pass gives each active thread two consecutive blocks of E outputs, so
@@ -652,10 +659,8 @@ __device__ __forceinline__ void block_sort(T *lds, uint32_t P, uint32_t R0 = E) 
                         : dpp16   ? 16 * E
                         : dpp     ? 8 * E
                                   : E;
-    // keys-only 32-bit merges with 16 items per thread run on the bitonic layout (odd runs
-    // stored descending; with 20 or 32 items per thread it raised the bucket kernels' VGPRs
-    // from 69 to 85 and more and lost there)
-    constexpr bool BIT = sizeof(T) == 4 && !COMP && E == 16;
+    // keys-only 32-bit merges run on the bitonic layout (odd runs stored descending)
+    constexpr bool BIT = sizeof(T) == 4 && !COMP;
     T x[E];
     if (R0 <= E && act) {
 #pragma unroll

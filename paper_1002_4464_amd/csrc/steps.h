@@ -343,10 +343,12 @@ __global__ __launch_bounds__(CAP / E) void k_sort_samples(const SC *src, SC *dst
         }
     }
     __syncthreads();
-    // Each sublist's s samples are already in order (they come from its sorted items) and
-    // every range starts on a row, so the sort starts from runs of s; sample composites are
-    // in position order.
-    block_sort<SC, E, true>(lds, P, s > (uint32_t)E ? s : (uint32_t)E);
+    // Each sublist's s samples are already in order (they come from its sorted items), and
+    // every range starts on a row (a segment's) or at a multiple of CAP (fixed chunks), so the
+    // sort starts from the aligned runs of the largest power of two r dividing s: no row
+    // boundary falls inside one.  Sample composites are in position order.
+    const uint32_t r = s & (0u - s);
+    block_sort<SC, E, true>(lds, P, r > (uint32_t)E ? r : (uint32_t)E);
     for (uint32_t i = tid; i < count; i += blockDim.x) dst[begin + i] = lds[pidx<SC>(i)];
 }
 
@@ -754,18 +756,21 @@ __global__ __launch_bounds__(1024) void k_scan_mid(uint32_t *partial, uint32_t n
                                                    Classes cls, uint32_t limit,
                                                    uint32_t *ovf_count, uint32_t *ovf_list) {
     __shared__ uint32_t colsum[1024], colbase[1024], tmp[1024];
-    const uint32_t ng = blockDim.x / s;  // s divides blockDim (both powers of two, s <= 1024)
+    // s <= blockDim: ng groups of s threads; the threads past the last whole group only join
+    // the barriers
+    const uint32_t ng = blockDim.x / s;
     const uint32_t grp = threadIdx.x / s, j = threadIdx.x % s;
+    const bool live = grp < ng;
     const uint32_t per = (nrb + ng - 1) / ng;
-    const uint32_t b0 = min(nrb, grp * per), b1 = min(nrb, b0 + per);
+    const uint32_t b0 = live ? min(nrb, grp * per) : nrb, b1 = live ? min(nrb, b0 + per) : nrb;
     uint32_t own = 0;
 #pragma unroll 8
     for (uint32_t b = b0; b < b1; ++b) own += partial[(size_t)b * s + j];
-    tmp[grp * s + j] = own;
+    if (live) tmp[grp * s + j] = own;
     __syncthreads();
     uint32_t run = 0;
-    for (uint32_t q = 0; q < grp; ++q) run += tmp[q * s + j];
-    if (grp == ng - 1) {
+    for (uint32_t q = 0; live && q < grp; ++q) run += tmp[q * s + j];
+    if (live && grp == ng - 1) {
         colsum[j] = run + own;
         colbase[j] = run + own;
     }

@@ -43,9 +43,18 @@ def test_plan_rejects_bad_arguments():
     assert lib.dsort_plan(ctypes.byref(h), 1, 2, 100, 0, None, ctypes.byref(ws)) == ds.E_INVALID
     assert lib.dsort_plan(ctypes.byref(h), 1, 0, 1 << 33, 0, None,
                           ctypes.byref(ws)) == ds.E_INVALID
-    bad = ds.Tuning(1000, 0, 0, 0, 0)  # not a power of two
-    assert lib.dsort_plan(ctypes.byref(h), 1, 0, 1 << 20, 0, ctypes.byref(bad),
-                          ctypes.byref(ws)) == ds.E_UNSUPPORTED
+    # a sublist length must be a power of two or a multiple of 64 items per thread (1024 for
+    # 32-bit keys), and the sample count must divide it
+    for t in [(1000, 0, 0, 0, 0), (15360 + 512, 0, 0, 0, 0), (15360, 300, 0, 0, 0),
+              (16384, 256, 7000, 0, 2), (16384, 256, 15360, 100, 2)]:
+        bad = ds.Tuning(*t)
+        assert lib.dsort_plan(ctypes.byref(h), 1, 0, 1 << 20, 0, ctypes.byref(bad),
+                              ctypes.byref(ws)) == ds.E_UNSUPPORTED, t
+    for t in [(15360, 320, 16384, 128, 2), (3072, 96, 0, 0, 0), (16384, 256, 15360, 120, 2)]:
+        good = ds.Tuning(*t)
+        assert lib.dsort_plan(ctypes.byref(h), 1, 0, 1 << 20, 0, ctypes.byref(good),
+                              ctypes.byref(ws)) == ds.OK, t
+        lib.dsort_plan_destroy(h)
     bad = ds.Tuning(1024, 4, 0, 0, 1)  # one level but buckets would exceed a workgroup
     assert lib.dsort_plan(ctypes.byref(h), 1, 0, 1 << 24, 0, ctypes.byref(bad),
                           ctypes.byref(ws)) == ds.E_UNSUPPORTED

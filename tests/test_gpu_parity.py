@@ -286,6 +286,31 @@ def test_module_sort_on_two_streams(ds):
             assert (from_dev(t, np.uint32) == w).all()
 
 
+@pytest.mark.parametrize("case", [
+    # (key type, pairs, n, (L1, s1, L2, s2, levels)): sublist lengths that are not powers of two
+    # (multiples of 64 items per thread) and sample counts that are not either (Step 4 then
+    # starts from the largest power-of-two runs dividing s; chunks of the global sample sort
+    # cut rows of s)
+    (1, False, 300_007, (3072, 96, 0, 0, 1)),
+    (1, False, 1_000_003, (15360, 320, 5120, 80, 2)),
+    (2, True, 400_009, (7680, 640, 1536, 48, 2)),
+], ids=["u32_one_L3072_s96", "u32_two_L15360_s320", "u64pairs_two_L7680_s640"])
+def test_non_power_of_two_plans(ds, case):
+    kt, pairs, n, t = case
+    say(f"non-power-of-two plan kt={kt} pairs={pairs} n={n} tuning={t}")
+    keys = synth.uniform_u32(n, 83) if kt == 1 else synth.zipf_u64(n, 84, distinct=1 << 14)
+    vals = synth.index_values(n) if pairs else None
+    out_k, out_v, geo, ws = gpu_sort(ds, keys, vals, tuning=ds.Tuning(*t))
+    assert (geo.sublist_len, geo.samples, geo.levels) == (t[0], t[1], t[4])
+    if t[4] == 2:
+        assert (geo.sublist_len2, geo.samples2) == (t[2], t[3])
+    ok, ov, tr = oracle.dss(keys, t[0], t[1], values=vals, trace=True)
+    assert (out_k == ok).all()
+    if pairs:
+        assert (out_v == ov).all()
+    check_level1(geo, ws, tr, n)
+
+
 # ------------------------------------------------------------------ the headline plan's depth
 
 @pytest.mark.parametrize("case", [
