@@ -114,8 +114,8 @@ int dsort_pairs(dsort_plan_t plan, void *d_keys, uint32_t *d_values, uint64_t n,
  * per GPU, created when the library's code is loaded on that GPU and held until the process
  * ends; the call itself allocates nothing, host or device.  `n` is limited to sizes whose
  * workspace (dsort_plan_geometry's workspace_bytes under the automatic plan) fits the array:
- * 15,428,032 uint32/float32 keys, 8,083,264 32-bit keys with values, 7,944,672 uint64 keys
- * and 5,131,264 uint64 keys with values.  Every call on one GPU shares that GPU's array, so calls
+ * 13,801,792 uint32/float32 keys, 7,615,552 32-bit keys with values, 7,086,432 uint64 keys
+ * and 4,940,832 uint64 keys with values.  Every call on one GPU shares that GPU's array, so calls
  * that overlap on one GPU (two streams, two host threads) race and corrupt each other; calls
  * must be ordered (one stream, or synchronised).  The array keeps the last call's
  * intermediates; each call clears what it needs cleared on the device.

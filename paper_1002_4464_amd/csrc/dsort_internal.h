@@ -61,6 +61,8 @@ struct Geom {
     size_t o_samp2 = 0, o_samp2_sorted = 0, o_counts2 = 0, o_offs2 = 0, o_pdst2 = 0, o_psrc2 = 0;
     size_t o_final = 0, o_lists = 0;
     size_t o_ovf = 0;  // randomized: the level-1 buckets routed to the further run
+    // rank index of each level's sorted sublists: the key at every 16th rank (0 = none)
+    size_t o_idx1 = 0, o_idx2 = 0;
     size_t total = 0;
 };
 

@@ -367,7 +367,7 @@ template <class K, bool V, bool F32> struct Pipeline {
             if (rc) return rc;
             DS_LAUNCH("s56_rank", (k_rank<K, V>), dim3(q.tiles_max), dim3(256),
                       (const K *)wkeys, (const void *)sorted, (const void *)samp, counts, sv,
-                      q.L, q.s, 0u);
+                      q.L, q.s, 0u, (const K *)nullptr);
             DS_LAUNCH("s7_scan", k_scan_seg, dim3(q.gmax), dim3(256), (const uint32_t *)counts,
                       offs, pdst, psrc, sv, q.L, q.s, finals, fcls);
             GatherArgs a{wkeys, keys, wvals, d_vals, finals, pdst, psrc, fcls.count, lists,
@@ -421,7 +421,7 @@ template <class K, bool V, bool F32> struct Pipeline {
         // Steps 1-3
         {
             TileArgs a{keys, tiles, d_vals, tvals, sv1, g.L1, g.s1, samp, status, nullptr,
-                       nullptr, g.seed, rnd};
+                       nullptr, g.seed, rnd, g.o_idx1 ? (void *)(ws + g.o_idx1) : nullptr};
             DS_LAUNCH("s123_local_sort", (k_tile<K, V, TE, TCAP, MODE_SAMPLE, F32, false>),
                       dim3(g.m1), dim3(g.L1 / TE), a);
         }
@@ -432,7 +432,8 @@ template <class K, bool V, bool F32> struct Pipeline {
         if (rc) return rc;
         // Steps 5-6
         DS_LAUNCH("s56_rank", (k_rank<K, V>), dim3(g.m1), dim3(256), (const K *)tiles,
-                  (const void *)sorted, (const void *)samp, counts, sv1, g.L1, g.s1, rnd);
+                  (const void *)sorted, (const void *)samp, counts, sv1, g.L1, g.s1, rnd,
+                  g.o_idx1 ? (const K *)(ws + g.o_idx1) : (const K *)nullptr);
         // Step 7
         DS_LAUNCH("s7_scan_colsum", k_scan_partial, dim3(g.scan_nrb), dim3(256),
                   (const uint32_t *)counts, partial, g.m1, g.s1, g.scan_rb);
@@ -475,7 +476,8 @@ template <class K, bool V, bool F32> struct Pipeline {
         uint32_t *psrc2 = (uint32_t *)(ws + g.o_psrc2);
         uint4 *finals = (uint4 *)(ws + g.o_final);
         {
-            TileArgs a{keys, wkeys, d_vals, wvals, sv2, g.L2, g.s2, samp2, status, pdst, psrc};
+            TileArgs a{keys, wkeys, d_vals, wvals, sv2, g.L2, g.s2, samp2, status, pdst, psrc, 0, 0,
+                       g.o_idx2 ? (void *)(ws + g.o_idx2) : nullptr};
             DS_LAUNCH("s8_l2_s123_gather_sort",
                       (k_tile<K, V, TE, TCAP, MODE_SAMPLE, false, false, true>),
                       dim3(g.tiles2max), dim3(g.L2 / TE), a);
@@ -484,7 +486,8 @@ template <class K, bool V, bool F32> struct Pipeline {
                           tm, "l2_s4_sample_sort", "l2_s4_sample_merge");
         if (rc) return rc;
         DS_LAUNCH("l2_s56_rank", (k_rank<K, V>), dim3(g.tiles2max), dim3(256), (const K *)wkeys,
-                  (const void *)sorted2, (const void *)samp2, counts2, sv2, g.L2, g.s2, 0u);
+                  (const void *)sorted2, (const void *)samp2, counts2, sv2, g.L2, g.s2, 0u,
+                  g.o_idx2 ? (const K *)(ws + g.o_idx2) : (const K *)nullptr);
         DS_LAUNCH("l2_s7_scan", k_scan_seg, dim3(g.s1), dim3(256), (const uint32_t *)counts2,
                   offs2, pdst2, psrc2, sv2, g.L2, g.s2, finals, cls);
         GatherArgs a{wkeys, keys, wvals, d_vals, finals, pdst2, psrc2, status + 1, lists,

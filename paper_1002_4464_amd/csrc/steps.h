@@ -27,6 +27,7 @@ struct TileArgs {
     const uint32_t *psrc;  // GIN: their source positions in src_keys / src_vals
     uint64_t seed;         // MODE_SAMPLE without GIN, random != 0: the samples' stream seed
     uint32_t random;       // 1: Step 3 takes s random sorted positions instead of chunk ends
+    void *rank_idx;        // MODE_SAMPLE, optional: L/16 keys per tile, the key at rank 16q+15
 };
 
 // Sublists of a second level read straight from the pieces of the first (Step 8 of the first
@@ -267,6 +268,11 @@ __global__ __launch_bounds__(CAP / E, (tile_waves_per_eu<K, V, E, CAP>())) void 
             dst[begin + i] = k;
         }
     }
+    if (MODE == MODE_SAMPLE && a.rank_idx) {
+        // the rank index of Steps 5-6: every 16th key of the sorted sublist (pads: key-max)
+        K *ix = (K *)a.rank_idx + (size_t)(loc.tile0 + loc.i) * (a.L / 16);
+        for (uint32_t q = tid; q < a.L / 16; q += bd) ix[q] = R::key(lds[pidx<T>(16 * q + 15)]);
+    }
     if constexpr (V) {
         __syncthreads();
         if (GIN)
@@ -470,11 +476,62 @@ __device__ __forceinline__ void rank_chunks(const K *keys, const typename Tr<K, 
     }
 }
 
+// The same counts through the rank index (every 16th key of each sorted sublist, at rank
+// 16q + 15): per global sample, one lane per index entry of its chunk counts the entries <= g_j
+// (each is the largest item of its block of 16, so that many whole blocks precede the rank),
+// then 16 lanes count inside the one block that holds the rank.  About 16 + w/4 bytes per
+// (sublist, splitter) pair are read instead of 4w (32-bit keys).  w = 16 nb, 8 <= nb <= 64.
+template <class K, bool V>
+__device__ __forceinline__ void rank_blocks(const K *keys, const K *ix,
+                                            const typename Tr<K, V>::SC *S, uint32_t m,
+                                            const uint32_t *chunk, uint32_t *rk, uint32_t s,
+                                            uint32_t w, uint32_t base, uint32_t count,
+                                            uint32_t p0) {
+    using R = Tr<K, V>;
+    using SC = typename R::SC;
+    const uint32_t lane = threadIdx.x & 63, nwv = blockDim.x >> 6;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t nb = w / 16;
+    for (uint32_t j0 = wv * kRankBatch; j0 < s; j0 += nwv * kRankBatch) {
+        K v[kRankBatch];
+        uint32_t cc[kRankBatch];
+        SC gg[kRankBatch];
+#pragma unroll
+        for (uint32_t u = 0; u < kRankBatch; ++u) {
+            cc[u] = j0 + u < s ? __builtin_amdgcn_readfirstlane(chunk[j0 + u]) : s;
+            gg[u] = cc[u] < s ? S[(size_t)(j0 + u + 1) * m - 1] : SC{};
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kRankBatch; ++u)
+            v[u] = (cc[u] < s && lane < nb) ? ix[cc[u] * nb + lane] : KeyMax<K>::v;
+        uint32_t bb[kRankBatch];  // blocks wholly <= g_j (wave-uniform)
+#pragma unroll
+        for (uint32_t u = 0; u < kRankBatch; ++u) {
+            const bool in = lane < nb && !lt(gg[u], R::samp(v[u], p0 + cc[u] * w + 16 * lane + 15));
+            bb[u] = (uint32_t)__popcll(__ballot(in));
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kRankBatch; ++u) {
+            const uint32_t x = cc[u] * w + 16 * bb[u] + lane;
+            v[u] = (cc[u] < s && lane < 16 && x < count) ? keys[base + x] : KeyMax<K>::v;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kRankBatch; ++u) {
+            const uint32_t c = cc[u];
+            if (c >= s) continue;
+            const uint32_t x0 = c * w + 16 * bb[u];
+            const bool in = lane < 16 && !lt(gg[u], R::samp(v[u], p0 + x0 + lane));
+            const uint32_t le = (uint32_t)__popcll(__ballot(in));
+            if (lane == 0) rk[j0 + u + 1] = x0 + le;
+        }
+    }
+}
+
 template <class K, bool V>
 __global__ __launch_bounds__(256) void k_rank(const K *keys, const void *sorted_samples,
                                               const void *tile_samples, uint32_t *counts,
                                               SegView sv, uint32_t L, uint32_t s,
-                                              uint32_t random) {
+                                              uint32_t random, const K *rank_idx) {
     using R = Tr<K, V>;
     using SC = typename R::SC;
     __shared__ uint32_t rk[1025], chunk[1024];
@@ -531,7 +588,10 @@ __global__ __launch_bounds__(256) void k_rank(const K *keys, const void *sorted_
     }
     if (threadIdx.x == 0) rk[0] = 0;
     __syncthreads();
-    if (w <= 64) {
+    if (rank_idx && w % 16 == 0 && w >= 128 && w <= 1024) {
+        rank_blocks<K, V>(keys, rank_idx + (size_t)(loc.tile0 + loc.i) * (L / 16), S, loc.m,
+                          chunk, rk, s, w, base, count, p0);
+    } else if (w <= 64) {
         rank_chunks<K, V, 1>(keys, S, loc.m, chunk, rk, s, w, base, count, p0);
     } else if (w <= 128) {
         rank_chunks<K, V, 2>(keys, S, loc.m, chunk, rk, s, w, base, count, p0);

@@ -276,8 +276,8 @@ def test_largest_plannable_sizes():
         assert ok(kt, v, limit) and not ok(kt, v, limit + 1)
 
 
-NOALLOC_LIMITS = [(ds.U32, 0, 15_428_032), (ds.F32, 0, 15_428_032), (ds.U32, 1, 8_083_264),
-                  (ds.U64, 0, 7_944_672), (ds.U64, 1, 5_131_264)]
+NOALLOC_LIMITS = [(ds.U32, 0, 13_801_792), (ds.F32, 0, 13_801_792), (ds.U32, 1, 7_615_552),
+                  (ds.U64, 0, 7_086_432), (ds.U64, 1, 4_940_832)]
 
 
 @pytest.mark.parametrize("kt,values,limit", NOALLOC_LIMITS)

@@ -124,6 +124,8 @@ CASES = [
     (9_999, 256, 8),
     (100_003, 1024, 256),  # m*s > one workgroup: Step 4 by chunk sorts + merge rounds
     (16_385, 16384, 64),   # last sublist holds a single real item, the rest pads
+    (200_003, 4096, 16),   # chunks of 256 items: ranks through the 16-item rank index
+    (120_001, 16384, 16),  # chunks of 1024 items: 64 index entries per chunk, the most it takes
 ]
 
 

@@ -12,8 +12,8 @@ from helpers import from_dev, say, to_dev
 pytestmark = pytest.mark.gpu
 
 # Largest n per layout whose automatic-plan workspace fits the 64 MiB array.
-LIMITS = {("u32", False): 15_428_032, ("u32", True): 8_083_264, ("u64", False): 7_944_672,
-          ("u64", True): 5_131_264}
+LIMITS = {("u32", False): 13_801_792, ("u32", True): 7_615_552, ("u64", False): 7_086_432,
+          ("u64", True): 4_940_832}
 
 
 @pytest.fixture(scope="module")
