@@ -67,18 +67,32 @@ def group_bytes(group: str, n: int, g, kb: int) -> float:
     """Algorithmic HBM bytes one step of a stage group must move:
     a sort or move of the data reads and writes n keys once; ranking reads the sorted sublists
     once plus the splitters and writes the counts; the scan reads the m x s counts twice (column
-    sums, then the update) and writes the offsets, piece destinations and piece sources."""
+    sums, then the update) and writes the offsets, piece destinations and piece sources.
+    Where a level's chunks hold w = L/s of 128 to 1024 items (a multiple of 16, chunk-end
+    samples), its tile sort also writes the rank index (every 16th key, n/16 keys) and each
+    (sublist, splitter) rank reads w/16 index entries and one block of 16 keys instead of the
+    chunk."""
     sb = g.sample_bytes
     m1s1 = g.sublists * g.samples
     m2s2 = -(-n // max(g.sublist_len2, 1)) * g.samples2 if g.levels == 2 else 0
+
+    def index_w(L, s):
+        w = L // s if s else 0
+        return w if (w % 16 == 0 and 128 <= w <= 1024 and not g.sampling) else 0
+
+    w1 = index_w(g.sublist_len, g.samples)
+    w2 = index_w(g.sublist_len2, g.samples2) if g.levels == 2 else 0
+    rank1 = m1s1 * (w1 // 16 + 16) * kb if w1 else n * kb
+    rank2 = m2s2 * (w2 // 16 + 16) * kb if w2 else n * kb
     return {
-        "steps1-3 local sort + sampling": 2 * n * kb + m1s1 * sb,
+        "steps1-3 local sort + sampling": 2 * n * kb + m1s1 * sb + (n * kb // 16 if w1 else 0),
         "step4 sample sort": 2 * m1s1 * sb,
-        "steps5-6 rank": n * kb + m1s1 * (sb + 4),
+        "steps5-6 rank": rank1 + m1s1 * (sb + 4),
         "step7 scan": 5 * m1s1 * 4,
-        "step8 + level2 steps1-3": 2 * n * kb + 2 * m1s1 * 4 + m2s2 * sb,
+        "step8 + level2 steps1-3": (2 * n * kb + 2 * m1s1 * 4 + m2s2 * sb
+                                    + (n * kb // 16 if w2 else 0)),
         "level2 step4": 2 * m2s2 * sb,
-        "level2 steps5-6": n * kb + m2s2 * (sb + 4),
+        "level2 steps5-6": rank2 + m2s2 * (sb + 4),
         "level2 step7": 5 * m2s2 * 4,
         "steps8-9 gather + bucket sort": 2 * n * kb,
     }.get(group, 0.0)
