@@ -162,6 +162,14 @@ template <class T> struct GatherVals {
 template <class K, bool V, int E, int CAP>
 constexpr int tile_waves_per_eu() { return !V && sizeof(K) == 4 && CAP / E == 1024 ? 8 : 1; }
 
+// 128-bit loads and stores of a tile's 32-bit keys: for whole tiles (count = P, a multiple of
+// 4 * blockDim when P = E * blockDim) whose keys start on a 16-byte boundary.
+template <class K, int E>
+__device__ __forceinline__ bool tile_vec4(const K *p, uint32_t count, uint32_t P) {
+    return sizeof(K) == 4 && E % 4 == 0 && count == P && P == E * blockDim.x &&
+           ((uintptr_t)p & 15) == 0;
+}
+
 template <class K, bool V, int E, int CAP, int MODE, bool XIN, bool XOUT, bool GIN = false>
 __global__ __launch_bounds__(CAP / E, (tile_waves_per_eu<K, V, E, CAP>())) void k_tile(TileArgs a) {
     using R = Tr<K, V>;
@@ -209,6 +217,22 @@ __global__ __launch_bounds__(CAP / E, (tile_waves_per_eu<K, V, E, CAP>())) void 
         tile_gather(a.pdst + loc.piece0, a.psrc + loc.piece0, loc.seg_begin, loc.i * a.L, count,
                     p_first, p_last, tb, sb, GatherKeys<K, R, T>{src, lds, a.sv.n_total});
         for (uint32_t i = count + tid; i < P; i += bd) lds[pidx<T>(i)] = R::pad(i);
+    } else if (tile_vec4<K, E>(src + begin, count, P)) {
+        // whole tile, 16-byte aligned: four keys per 128-bit load, consecutive lanes on
+        // consecutive 16-byte words, all of a thread's loads in flight together (four items
+        // 4j..4j+3 never straddle an LDS pad)
+        uint4 v[E / 4];
+        const uint4 *s4 = (const uint4 *)(src + begin);
+#pragma unroll
+        for (int q = 0; q < E / 4; ++q) v[q] = s4[tid + q * bd];
+#pragma unroll
+        for (int q = 0; q < E / 4; ++q) {
+            const uint32_t i = 4 * (tid + q * bd);
+            T *d = lds + pidx<T>(i);
+            const uint32_t w[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) d[r] = R::make(XIN ? (K)f32_in(w[r]) : (K)w[r], i + r);
+        }
     } else {
         // P <= E * blockDim.x: every thread's E loads are issued before any is waited for
         K v[E];
@@ -259,13 +283,29 @@ __global__ __launch_bounds__(CAP / E, (tile_waves_per_eu<K, V, E, CAP>())) void 
     }
 
     K *dst = (K *)a.dst_keys;
+    if (tile_vec4<K, E>(dst + begin, count, P)) {
+        uint4 *d4 = (uint4 *)(dst + begin);
 #pragma unroll 2
-    for (int q = 0; q < E; ++q) {
-        const uint32_t i = tid + q * bd;
-        if (i < count) {
-            K k = R::key(lds[pidx<T>(i)]);
-            if (XOUT) k = (K)f32_out((uint32_t)k);
-            dst[begin + i] = k;
+        for (int q = 0; q < E / 4; ++q) {
+            const uint32_t i = 4 * (tid + q * bd);
+            const T *l = lds + pidx<T>(i);
+            uint32_t w[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const K k = R::key(l[r]);
+                w[r] = (uint32_t)(XOUT ? (K)f32_out((uint32_t)k) : k);
+            }
+            d4[tid + q * bd] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+    } else {
+#pragma unroll 2
+        for (int q = 0; q < E; ++q) {
+            const uint32_t i = tid + q * bd;
+            if (i < count) {
+                K k = R::key(lds[pidx<T>(i)]);
+                if (XOUT) k = (K)f32_out((uint32_t)k);
+                dst[begin + i] = k;
+            }
         }
     }
     if (MODE == MODE_SAMPLE && a.rank_idx) {
