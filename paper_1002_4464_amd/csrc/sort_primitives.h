@@ -605,7 +605,9 @@ __device__ __forceinline__ void serial_merge_bit(const uint32_t *lds, uint32_t &
 
 // Stores E registers into the block lds[blk, blk + E) (blk a multiple of E; padded indexing),
 // in order or reversed.  When E is a power of two within one padding period the block never
-// straddles a pad, so each store is one immediate offset from a common address.
+// straddles a pad, so each store is one immediate offset from a common address.  Otherwise
+// every item's padded index is computed, walking the block upwards or downwards with one
+// code path for both (two branches would both run in waves holding pairs of either parity).
 template <class T, int E>
 __device__ __forceinline__ void store_block(T *lds, uint32_t blk, bool rev, const T (&x)[E]) {
     if constexpr ((E & (E - 1)) == 0 && E <= (1 << PadShift<T>::v)) {
@@ -618,12 +620,15 @@ __device__ __forceinline__ void store_block(T *lds, uint32_t blk, bool rev, cons
 #pragma unroll
             for (int k = 0; k < E; ++k) p[k] = x[k];
         }
-    } else if (rev) {
-#pragma unroll
-        for (int k = 0; k < E; ++k) lds[pidx<T>(blk + E - 1 - k)] = x[k];
     } else {
+        uint32_t i = rev ? blk + E - 1 : blk;
+        uint32_t step = rev ? 0xFFFFFFFFu : 1u;
+        asm volatile("" : "+v"(i), "+v"(step));
 #pragma unroll
-        for (int k = 0; k < E; ++k) lds[pidx<T>(blk + k)] = x[k];
+        for (int k = 0; k < E; ++k) {
+            lds[pidx<T>(i)] = x[k];
+            i += step;
+        }
     }
 }
 
