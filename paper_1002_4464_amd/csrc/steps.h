@@ -466,7 +466,9 @@ __global__ __launch_bounds__(CAP / E) void k_merge_round(const SC *src, SC *dst,
 // the s samples in LDS, one thread per j).  Then, for w <= 128, each wave counts inside the
 // chunks of kRankBatch global samples at a time: all 64 lanes read one chunk's items with
 // coalesced loads and a ballot counts those <= g_j, the loads of the whole batch in flight
-// together (chunks shared by neighbouring samples come from cache).  Larger chunks are
+// together (chunks shared by neighbouring samples come from cache); chunks of at most 16
+// items take four samples per wave load, one per 16-lane group.  Chunks of 128 to 1024 items
+// read a rank index instead when the tile sort wrote one (rank_blocks); other large chunks are
 // bisected in global memory, one probe per step.  Pads (x >= count) are key-max items.
 constexpr uint32_t kRankBatch = 8;
 
@@ -512,6 +514,46 @@ __device__ __forceinline__ void rank_chunks(const K *keys, const typename Tr<K, 
                 le += (uint32_t)__popcll(__ballot(in));
             }
             if (lane == 0) rk[j + 1] = c * w + le;
+        }
+    }
+}
+
+// The chunk counts for chunks of at most 16 items: each 16-lane group of a wave takes its own
+// global sample, so one load instruction covers four samples' chunks (kRankBatch loads in
+// flight per lane: 4 kRankBatch samples per wave and batch).
+template <class K, bool V>
+__device__ __forceinline__ void rank_chunks16(const K *keys, const typename Tr<K, V>::SC *S,
+                                              uint32_t m, const uint32_t *chunk, uint32_t *rk,
+                                              uint32_t s, uint32_t w, uint32_t base,
+                                              uint32_t count, uint32_t p0) {
+    using R = Tr<K, V>;
+    using SC = typename R::SC;
+    const uint32_t lane = threadIdx.x & 63, nwv = blockDim.x >> 6;
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t g = lane >> 4, y = lane & 15;
+    constexpr uint32_t kB = 4 * kRankBatch;  // samples per wave and batch
+    for (uint32_t j0 = wv * kB; j0 < s; j0 += nwv * kB) {
+        K v[kRankBatch];
+        uint32_t cc[kRankBatch];
+        SC gg[kRankBatch];
+#pragma unroll
+        for (uint32_t u = 0; u < kRankBatch; ++u) {
+            const uint32_t j = j0 + 4 * u + g;  // this lane group's sample
+            cc[u] = j < s ? chunk[j] : s;
+            gg[u] = cc[u] < s ? S[(size_t)(j + 1) * m - 1] : SC{};
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kRankBatch; ++u) {
+            const uint32_t x = cc[u] * w + y;
+            v[u] = (cc[u] < s && y < w && x < count) ? keys[base + x] : KeyMax<K>::v;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kRankBatch; ++u) {
+            const uint32_t c = cc[u];
+            const bool in = c < s && y < w && !lt(gg[u], R::samp(v[u], p0 + c * w + y));
+            const uint64_t bits = __ballot(in) >> (16 * g);
+            const uint32_t le = (uint32_t)__popcll(bits & 0xFFFFull);
+            if (c < s && y == 0) rk[j0 + 4 * u + g + 1] = c * w + le;
         }
     }
 }
@@ -631,6 +673,8 @@ __global__ __launch_bounds__(256) void k_rank(const K *keys, const void *sorted_
     if (rank_idx && w % 16 == 0 && w >= 128 && w <= 1024) {
         rank_blocks<K, V>(keys, rank_idx + (size_t)(loc.tile0 + loc.i) * (L / 16), S, loc.m,
                           chunk, rk, s, w, base, count, p0);
+    } else if (w <= 16) {
+        rank_chunks16<K, V>(keys, S, loc.m, chunk, rk, s, w, base, count, p0);
     } else if (w <= 64) {
         rank_chunks<K, V, 1>(keys, S, loc.m, chunk, rk, s, w, base, count, p0);
     } else if (w <= 128) {
