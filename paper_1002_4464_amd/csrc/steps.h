@@ -91,15 +91,21 @@ __device__ __forceinline__ void tile_gather(const uint32_t *pdst, const uint32_t
             }
             p = l;
         }
-        // eight rows of the wave's share per pass: their loads are in flight together
+        // eight rows of the wave's share per pass: their loads are in flight together.  The
+        // lane's piece end and source offset stay in registers until it enters the next piece.
+        uint32_t pend = tb[p + 1], soff = sb[p];
         for (uint32_t row = xs; row < xe; row += 8 * wl) {
             uint32_t si[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const uint32_t xu = row + wl * u + lane;
                 if (xu < xe) {
-                    while (xu >= tb[p + 1]) ++p;
-                    si[u] = sb[p] + xu;
+                    while (xu >= pend) {
+                        ++p;
+                        pend = tb[p + 1];
+                        soff = sb[p];
+                    }
+                    si[u] = soff + xu;
                 }
             }
             store.template run<8>(row + lane, wl, xe, si);
@@ -1045,14 +1051,21 @@ __global__ __launch_bounds__((CAP / GatherE<K, V, CAP>::E), (GatherE<K, V, CAP>:
                 }
                 p = lo;
             }
+            // the lane's piece end and source offset (mod 2^32) stay in registers until it
+            // enters the next piece
+            uint32_t pend = bnd[p + 1], soff = ps[p] - bnd[p];
             for (uint32_t row = x_begin; row < x_end; row += 4 * 64) {
                 K v[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const uint32_t xu = row + 64 * u + lane;
                     if (xu < total) {
-                        while (xu >= bnd[p + 1]) ++p;
-                        v[u] = src[ps[p] + (xu - bnd[p])];
+                        while (xu >= pend) {
+                            ++p;
+                            pend = bnd[p + 1];
+                            soff = ps[p] - bnd[p];
+                        }
+                        v[u] = src[soff + xu];
                         if (XIN) v[u] = (K)f32_in((uint32_t)v[u]);
                     }
                 }
