@@ -168,12 +168,31 @@ template <class T> struct GatherVals {
 template <class K, bool V, int E, int CAP>
 constexpr int tile_waves_per_eu() { return !V && sizeof(K) == 4 && CAP / E == 1024 ? 8 : 1; }
 
-// 128-bit loads and stores of a tile's 32-bit keys: for whole tiles (count = P, a multiple of
-// 4 * blockDim when P = E * blockDim) whose keys start on a 16-byte boundary.
+// 128-bit loads and stores of a tile's keys (four 32-bit or two 64-bit keys per access): for
+// whole tiles (count = P = E * blockDim, E a multiple of the keys per access) whose keys start
+// on a 16-byte boundary.  The keys of one access never straddle an LDS pad.
+template <class K> struct Vec16 {
+    static constexpr int n = 16 / (int)sizeof(K);
+    static __device__ __forceinline__ void unpack(const uint4 &v, K (&k)[16 / sizeof(K)]) {
+        if constexpr (sizeof(K) == 4) {
+            k[0] = v.x; k[1] = v.y; k[2] = v.z; k[3] = v.w;
+        } else {
+            k[0] = ((uint64_t)v.y << 32) | v.x;
+            k[1] = ((uint64_t)v.w << 32) | v.z;
+        }
+    }
+    static __device__ __forceinline__ uint4 pack(const K (&k)[16 / sizeof(K)]) {
+        if constexpr (sizeof(K) == 4) {
+            return make_uint4(k[0], k[1], k[2], k[3]);
+        } else {
+            return make_uint4((uint32_t)k[0], (uint32_t)(k[0] >> 32), (uint32_t)k[1],
+                              (uint32_t)(k[1] >> 32));
+        }
+    }
+};
 template <class K, int E>
 __device__ __forceinline__ bool tile_vec4(const K *p, uint32_t count, uint32_t P) {
-    return sizeof(K) == 4 && E % 4 == 0 && count == P && P == E * blockDim.x &&
-           ((uintptr_t)p & 15) == 0;
+    return E % Vec16<K>::n == 0 && count == P && P == E * blockDim.x && ((uintptr_t)p & 15) == 0;
 }
 
 template <class K, bool V, int E, int CAP, int MODE, bool XIN, bool XOUT, bool GIN = false>
@@ -224,20 +243,22 @@ __global__ __launch_bounds__(CAP / E, (tile_waves_per_eu<K, V, E, CAP>())) void 
                     p_first, p_last, tb, sb, GatherKeys<K, R, T>{src, lds, a.sv.n_total});
         for (uint32_t i = count + tid; i < P; i += bd) lds[pidx<T>(i)] = R::pad(i);
     } else if (tile_vec4<K, E>(src + begin, count, P)) {
-        // whole tile, 16-byte aligned: four keys per 128-bit load, consecutive lanes on
-        // consecutive 16-byte words, all of a thread's loads in flight together (four items
-        // 4j..4j+3 never straddle an LDS pad)
-        uint4 v[E / 4];
+        // whole tile, 16-byte aligned: 128-bit loads, consecutive lanes on consecutive 16-byte
+        // words, all of a thread's loads in flight together
+        constexpr int NV = Vec16<K>::n;
+        uint4 v[E / NV];
         const uint4 *s4 = (const uint4 *)(src + begin);
 #pragma unroll
-        for (int q = 0; q < E / 4; ++q) v[q] = s4[tid + q * bd];
+        for (int q = 0; q < E / NV; ++q) v[q] = s4[tid + q * bd];
 #pragma unroll
-        for (int q = 0; q < E / 4; ++q) {
-            const uint32_t i = 4 * (tid + q * bd);
+        for (int q = 0; q < E / NV; ++q) {
+            const uint32_t i = NV * (tid + q * bd);
             T *d = lds + pidx<T>(i);
-            const uint32_t w[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+            K w[NV];
+            Vec16<K>::unpack(v[q], w);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) d[r] = R::make(XIN ? (K)f32_in(w[r]) : (K)w[r], i + r);
+            for (int r = 0; r < NV; ++r)
+                d[r] = R::make(XIN ? (K)f32_in((uint32_t)w[r]) : w[r], i + r);
         }
     } else {
         // P <= E * blockDim.x: every thread's E loads are issued before any is waited for
@@ -290,18 +311,19 @@ __global__ __launch_bounds__(CAP / E, (tile_waves_per_eu<K, V, E, CAP>())) void 
 
     K *dst = (K *)a.dst_keys;
     if (tile_vec4<K, E>(dst + begin, count, P)) {
+        constexpr int NV = Vec16<K>::n;
         uint4 *d4 = (uint4 *)(dst + begin);
 #pragma unroll 2
-        for (int q = 0; q < E / 4; ++q) {
-            const uint32_t i = 4 * (tid + q * bd);
+        for (int q = 0; q < E / NV; ++q) {
+            const uint32_t i = NV * (tid + q * bd);
             const T *l = lds + pidx<T>(i);
-            uint32_t w[4];
+            K w[NV];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
+            for (int r = 0; r < NV; ++r) {
                 const K k = R::key(l[r]);
-                w[r] = (uint32_t)(XOUT ? (K)f32_out((uint32_t)k) : k);
+                w[r] = XOUT ? (K)f32_out((uint32_t)k) : k;
             }
-            d4[tid + q * bd] = make_uint4(w[0], w[1], w[2], w[3]);
+            d4[tid + q * bd] = Vec16<K>::pack(w);
         }
     } else {
 #pragma unroll 2
