@@ -1116,10 +1116,43 @@ __global__ __launch_bounds__((CAP / GatherE<K, V, CAP>::E), (GatherE<K, V, CAP>:
         }
         if constexpr (V) {
             __syncthreads();
-            for (uint32_t i = w; i < np; i += nw) {
-                const uint32_t d0 = bnd[i], len = bnd[i + 1] - d0, s0 = ps[i];
-                for (uint32_t q = lane; q < len; q += 64)
-                    put_val<T>(lds, d0 + q, a.src_vals[s0 + q]);
+            // values by the keys' gather pattern: each wave streams its share of the bucket,
+            // every lane following the piece its item is in (whole waves busy even where the
+            // pieces are shorter than a wave)
+            const uint32_t span = ((total + nw - 1) / nw + 63) & ~63u;
+            const uint32_t x_begin = w * span, x_end = min(total, x_begin + span);
+            if (x_begin < x_end) {
+                uint32_t p = 0;
+                {
+                    uint32_t lo = 0, hi = np - 1;
+                    const uint32_t xs = min(x_begin + lane, total - 1);
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi + 1) >> 1;
+                        if (bnd[mid] <= xs) lo = mid; else hi = mid - 1;
+                    }
+                    p = lo;
+                }
+                uint32_t pend = bnd[p + 1], soff = ps[p] - bnd[p];
+                for (uint32_t row = x_begin; row < x_end; row += 4 * 64) {
+                    uint32_t vv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const uint32_t xu = row + 64 * u + lane;
+                        if (xu < x_end) {
+                            while (xu >= pend) {
+                                ++p;
+                                pend = bnd[p + 1];
+                                soff = ps[p] - bnd[p];
+                            }
+                            vv[u] = a.src_vals[soff + xu];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const uint32_t xu = row + 64 * u + lane;
+                        if (xu < x_end) put_val<T>(lds, xu, vv[u]);
+                    }
+                }
             }
             __syncthreads();
 #pragma unroll 2
