@@ -313,6 +313,39 @@ def test_non_power_of_two_plans(ds, case):
     check_level1(geo, ws, tr, n)
 
 
+@pytest.mark.parametrize("kind", ["u32", "u64_pairs"])
+def test_views_not_16_byte_aligned(ds, kind):
+    """Keys (and values) starting one element past an aligned address: whole tiles then take
+    the per-key loads and stores instead of the 128-bit ones, at both levels."""
+    import torch
+    n = 300_007
+    say(f"unaligned views {kind} n={n}")
+    if kind == "u32":
+        keys, vals, kt, L = synth.uniform_u32(n, 85), None, 1, 4096
+    else:
+        keys, vals, kt, L = synth.zipf_u64(n, 86, distinct=1 << 12), synth.index_values(n), 2, 2048
+    plan = ds.Plan(kt, vals is not None, n, ds.Tuning(L, 64, 0, 0, 2))
+    tk = to_dev(np.concatenate([keys[:1], keys]))[1:]
+    assert tk.data_ptr() % 16 != 0
+    ws = plan.workspace(tk.device)
+    if vals is None:
+        plan.sort_keys(tk, ws)
+        tv = None
+    else:
+        tv = to_dev(np.concatenate([vals[:1], vals]))[1:]
+        assert tv.data_ptr() % 16 != 0
+        plan.sort_pairs(tk, tv, ws)
+    torch.cuda.synchronize()
+    geo = plan.geometry(n)
+    assert geo.levels == 2
+    assert int(ws_view(ws, geo.off_status, 1, np.uint32)[0]) == 0
+    ok, ov, tr = oracle.dss(keys, L, 64, values=vals, trace=True)
+    assert (from_dev(tk, keys.dtype) == ok).all()
+    if vals is not None:
+        assert (from_dev(tv, np.uint32) == ov).all()
+    check_level1(geo, ws, tr, n)
+
+
 # ------------------------------------------------------------------ the headline plan's depth
 
 @pytest.mark.parametrize("case", [
