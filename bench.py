@@ -68,7 +68,7 @@ def group_bytes(group: str, n: int, g, kb: int) -> float:
     a sort or move of the data reads and writes n keys once; ranking reads the sorted sublists
     once plus the splitters and writes the counts; the scan reads the m x s counts twice (column
     sums, then the update) and writes the offsets, piece destinations and piece sources.
-    Where a level's chunks hold w = L/s of 128 to 1024 items (a multiple of 16, chunk-end
+    Where a level's chunks hold w = L/s of 64 to 1024 items (a multiple of 16, chunk-end
     samples), its tile sort also writes the rank index (every 16th key, n/16 keys) and each
     (sublist, splitter) rank reads w/16 index entries and one block of 16 keys instead of the
     chunk."""
@@ -78,9 +78,10 @@ def group_bytes(group: str, n: int, g, kb: int) -> float:
 
     def index_w(L, s):
         w = L // s if s else 0
-        return w if (w % 16 == 0 and 128 <= w <= 1024 and not g.sampling) else 0
+        return w if (w % 16 == 0 and 64 <= w <= 1024) else 0
 
-    w1 = index_w(g.sublist_len, g.samples)
+    # randomized plans bisect their level-1 ranks; their level 2 has chunk-end samples
+    w1 = 0 if g.sampling else index_w(g.sublist_len, g.samples)
     w2 = index_w(g.sublist_len2, g.samples2) if g.levels == 2 else 0
     rank1 = m1s1 * (w1 // 16 + 16) * kb if w1 else n * kb
     rank2 = m2s2 * (w2 // 16 + 16) * kb if w2 else n * kb

@@ -115,7 +115,7 @@ int dsort_pairs(dsort_plan_t plan, void *d_keys, uint32_t *d_values, uint64_t n,
  * ends; the call itself allocates nothing, host or device.  `n` is limited to sizes whose
  * workspace (dsort_plan_geometry's workspace_bytes under the automatic plan) fits the array:
  * 13,801,792 uint32/float32 keys, 7,615,552 32-bit keys with values, 7,086,432 uint64 keys
- * and 4,940,832 uint64 keys with values.  Every call on one GPU shares that GPU's array, so calls
+ * and 4,755,104 uint64 keys with values.  Every call on one GPU shares that GPU's array, so calls
  * that overlap on one GPU (two streams, two host threads) race and corrupt each other; calls
  * must be ordered (one stream, or synchronised).  The array keeps the last call's
  * intermediates; each call clears what it needs cleared on the device.

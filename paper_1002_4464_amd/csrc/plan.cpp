@@ -41,13 +41,12 @@ bool level_L_ok(const Caps &c, uint64_t L) {
 }
 bool level_s_ok(uint64_t s, uint64_t L) { return s && s <= L && s <= kMaxSamples && L % s == 0; }
 
-// Chunks of L/s items that the rank index serves: whole blocks of 16, at least 8 and at most
-// 64 of them (one lane per index entry).  Below 128 items the chunk is read whole: measured at
-// 2^28 u32, the index made the level-1 ranks (64-item chunks) slower, 0.28 -> 0.32 ms, and the
-// level-2 ranks (128-item chunks) faster, 0.225 -> 0.181 ms.
+// Chunks of L/s items that the rank index serves: whole blocks of 16, at least 4 and at most
+// 64 of them (one lane per index entry; up to 16 entries, four samples share a wave load).
+// Smaller chunks are read whole.
 bool rank_index_ok(uint64_t L, uint64_t s) {
     const uint64_t w = L / s;
-    return w % 16 == 0 && w >= 128 && w <= 1024;
+    return w % 16 == 0 && w >= 64 && w <= 1024;
 }
 
 }  // namespace

@@ -277,7 +277,7 @@ def test_largest_plannable_sizes():
 
 
 NOALLOC_LIMITS = [(ds.U32, 0, 13_801_792), (ds.F32, 0, 13_801_792), (ds.U32, 1, 7_615_552),
-                  (ds.U64, 0, 7_086_432), (ds.U64, 1, 4_940_832)]
+                  (ds.U64, 0, 7_086_432), (ds.U64, 1, 4_755_104)]
 
 
 @pytest.mark.parametrize("kt,values,limit", NOALLOC_LIMITS)

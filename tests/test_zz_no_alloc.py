@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 # Largest n per layout whose automatic-plan workspace fits the 64 MiB array.
 LIMITS = {("u32", False): 13_801_792, ("u32", True): 7_615_552, ("u64", False): 7_086_432,
-          ("u64", True): 4_940_832}
+          ("u64", True): 4_755_104}
 
 
 @pytest.fixture(scope="module")
