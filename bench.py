@@ -42,6 +42,7 @@ METRIC = "Mkeys/s + HBM GB/s (2^28 u32); p50/p99 latency, batched/served vs plai
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1002_4464_amd", "csrc", f)
                for f in ("kernels.hip", "steps.h", "sort_primitives.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+TRAFFIC_C3B_FILE = os.path.join(ROOT, "profiles", "traffic_c3b.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "valu.json")
 
 
@@ -107,11 +108,11 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(stage: str):
+def traffic_for(stage: str, path: str = TRAFFIC_FILE):
     """Measured HBM bytes per step of a stage group (rocprofv3 FETCH_SIZE + WRITE_SIZE, each
     scaled by a copy kernel of known size), if recorded for the current kernel source."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except OSError:
         return None
@@ -285,7 +286,7 @@ def distributions_leg(args, ds, torch, dev):
 def c3b_leg(args, ds, torch, dev):
     """2^27 (uint64 key, uint32 value = input index) pairs, keys uniform or Zipf(1.1) over 2^20
     values: time per sort, per-stage kernel times, and the dominant stage against the HBM
-    roofline (12 bytes per item)."""
+    roofline (12 bytes per item; measured traffic from profiles/traffic_c3b.json)."""
     import synth
     n = 1 << 27
     kb = 12
@@ -296,7 +297,7 @@ def c3b_leg(args, ds, torch, dev):
                        "or Zipf(1.1) over 2^20 values (seed 10), stable", "n": n,
            "plan": {"levels": g.levels, "L": g.sublist_len, "s": g.samples,
                     "L2": g.sublist_len2, "s2": g.samples2}}
-    for dist in ("uniform", "zipf"):
+    for dist in ("uniform",) if args.c3b_uniform_only else ("uniform", "zipf"):
         log(f"[bench] c3b: generating {dist}")
         keys = synth.uniform_u64(n, 9) if dist == "uniform" else synth.zipf_u64(n, 10)
         src = torch.from_numpy(keys.view(np.int64)).to(dev)
@@ -324,11 +325,13 @@ def c3b_leg(args, ds, torch, dev):
             ach = alg / (groups[dom] * 1e-3) / 1e9
             out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1),
                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                               "frac": round(ach / HBM_PEAK_GBS, 4),
+                               "traffic": traffic_for(dom, TRAFFIC_C3B_FILE),
                                "algorithmic_bytes": alg, "ms_per_step": groups[dom]}
         del src
         torch.cuda.empty_cache()
-    out["zipf_vs_uniform"] = round(out["zipf"]["ms"] / out["uniform"]["ms"], 4)
+    if "zipf" in out:
+        out["zipf_vs_uniform"] = round(out["zipf"]["ms"] / out["uniform"]["ms"], 4)
     return out
 
 
@@ -799,6 +802,17 @@ def ingest_valu(csv_path: str, sorts: int, out_json: str):
     print(json.dumps(rec, indent=1, sort_keys=True))
 
 
+def calibration_copy(args, torch, dev):
+    """With --copy-calibration BYTES: one device copy of that many bytes after the sorts, the
+    kernel of known size by which ingest_pmc scales the counters."""
+    if args.copy_calibration:
+        cs = torch.empty(args.copy_calibration // 4, dtype=torch.int32, device=dev)
+        cd = torch.empty_like(cs)
+        cd.copy_(cs)
+        torch.cuda.synchronize()
+        del cs, cd
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -817,6 +831,9 @@ def main():
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn two rocprofv3 counter CSVs of a --copy-calibration run into "
                          "profiles/traffic.json (CPU only)")
+    ap.add_argument("--traffic-file", default=TRAFFIC_FILE,
+                    help="where --ingest-pmc writes (profiles/traffic_c3b.json for a run of "
+                         "--only c3b --c3b-uniform-only)")
     ap.add_argument("--ingest-valu", metavar="PMC_CSV",
                     help="turn a rocprofv3 counter CSV holding SQ_INSTS_VALU into "
                          "profiles/valu.json (CPU only)")
@@ -835,6 +852,8 @@ def main():
                     help="seed of the randomized-splitter runs")
     ap.add_argument("--no-c3b", action="store_true", help="skip the 2^27 uint64-pair leg")
     ap.add_argument("--c3b-reps", type=int, default=5)
+    ap.add_argument("--c3b-uniform-only", action="store_true",
+                    help="the 2^27 uint64-pair leg without its Zipf input (for counter runs)")
     ap.add_argument("--only", choices=["batched", "served", "sweep", "distributions", "c3b"],
                     help="run only that leg and print its record (for profiling)")
     ap.add_argument("--served-requests", type=int, default=4000)
@@ -850,7 +869,7 @@ def main():
     args = ap.parse_args()
     if args.ingest_pmc:
         ingest_pmc(args.ingest_pmc[0], args.ingest_pmc[1], args.copy_calibration, args.sorts,
-                   TRAFFIC_FILE)
+                   args.traffic_file)
         return
     if args.ingest_valu:
         ingest_valu(args.ingest_valu, args.sorts, VALU_FILE)
@@ -870,7 +889,9 @@ def main():
     if args.only:
         leg = {"batched": batched_leg, "served": served_leg, "sweep": sweep,
                "distributions": distributions_leg, "c3b": c3b_leg}[args.only]
-        print(json.dumps({args.only: leg(args, ds, torch, dev)}), flush=True)
+        rec = leg(args, ds, torch, dev)
+        calibration_copy(args, torch, dev)
+        print(json.dumps({args.only: rec}), flush=True)
         return
     n = 1 << args.log2n
     K, W = args.steps, args.warmup
@@ -918,12 +939,7 @@ def main():
         dt_instr = time.perf_counter() - t1
         stages = plan.stage_times()
         plan.set_timing(False)
-    if args.copy_calibration:
-        cs = torch.empty(args.copy_calibration // 4, dtype=torch.int32, device=dev)
-        cd = torch.empty_like(cs)
-        cd.copy_(cs)
-        torch.cuda.synchronize()
-        del cs, cd
+    calibration_copy(args, torch, dev)
 
     out = bufs[-1][: 1 << 20].cpu().numpy().view(np.uint32)
     assert (out[1:] >= out[:-1]).all(), "output prefix not sorted"
